@@ -1,0 +1,138 @@
+"""CPU reference for the spherical harmonic transforms -- test infrastructure.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package; the GPU library never imports, links or calls it.
+
+It wraps ``sht_oracle.c`` (plain C99 + OpenMP, long double arithmetic with an
+extended exponent), which evaluates the paper's definitions directly:
+Eq. 10 + Eq. 11 for lambda, Eq. 4 and a direct per-ring DFT (Eq. 3) for
+synthesis, a direct per-ring DFT (Eq. 6) and Eq. 5 for analysis.  See the
+header comment of ``sht_oracle.c`` for conventions and layouts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sht_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math: IEEE semantics throughout)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_SO)
+        lib.oracle_lambda.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, _dp]
+        lib.oracle_lambda.restype = ctypes.c_int
+        lib.oracle_wigner_d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double]
+        lib.oracle_wigner_d.restype = ctypes.c_double
+        lib.oracle_synthesis.argtypes = [ctypes.c_int, _dp, _i64p, _dp, _i64p, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         _dp, _dp, ctypes.c_int, _ip, _dp]
+        lib.oracle_synthesis.restype = ctypes.c_int
+        lib.oracle_analysis.argtypes = [ctypes.c_int, _dp, _i64p, _dp, _dp, _i64p,
+                                        ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                        _ip, _dp]
+        lib.oracle_analysis.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, typ):
+    return a.ctypes.data_as(typ) if a is not None else None
+
+
+def lam(lmax: int, m: int, s: int, theta: float) -> np.ndarray:
+    """s_lambda_lm(theta) for l = 0..lmax (zero below max(|m|,|s|))."""
+    out = np.zeros(lmax + 1)
+    rc = _load().oracle_lambda(lmax, m, s, float(theta), _ptr(out, _dp))
+    if rc:
+        raise ValueError(f"oracle_lambda rc={rc}")
+    return out
+
+
+def wigner_d(j: int, mp: int, mm: int, beta: float) -> float:
+    return float(_load().oracle_wigner_d(j, mp, mm, float(beta)))
+
+
+def _geom_arrays(geom):
+    return (np.ascontiguousarray(geom.theta, dtype=np.float64),
+            np.ascontiguousarray(geom.nphi, dtype=np.int64),
+            np.ascontiguousarray(geom.phi0, dtype=np.float64),
+            np.ascontiguousarray(geom.weight, dtype=np.float64),
+            np.ascontiguousarray(geom.ofs, dtype=np.int64))
+
+
+def synthesis(geom, lmax: int, mmax: int, spin: int, alm: np.ndarray, rings=None,
+              want_phases: bool = False):
+    """alm float64 [ntrans][ncomp][nalm][2] -> map [ntrans][ncomp][npix]
+    (only the pixels of ``rings`` are filled when a subset is given).
+    With want_phases also returns F [ntrans][ncomp][nrings][mmax+1][2]."""
+    th, nph, p0, _, ofs = _geom_arrays(geom)
+    alm = np.ascontiguousarray(alm, dtype=np.float64)
+    ntrans, ncomp = alm.shape[0], alm.shape[1]
+    mp = np.zeros((ntrans, ncomp, geom.npix))
+    F = np.zeros((ntrans, ncomp, geom.nrings, mmax + 1, 2)) if want_phases else None
+    sel = None if rings is None else np.ascontiguousarray(rings, dtype=np.int32)
+    nsel = 0 if sel is None else int(sel.shape[0])
+    rc = _load().oracle_synthesis(geom.nrings, _ptr(th, _dp), _ptr(nph, _i64p), _ptr(p0, _dp),
+                                  _ptr(ofs, _i64p), int(geom.stride), lmax, mmax, spin,
+                                  ntrans, _ptr(alm, _dp), _ptr(mp, _dp), nsel,
+                                  _ptr(sel, _ip), _ptr(F, _dp))
+    if rc:
+        raise RuntimeError(f"oracle_synthesis rc={rc}")
+    return (mp, F) if want_phases else mp
+
+
+def analysis(geom, lmax: int, mmax: int, spin: int, maps: np.ndarray, weight=None, ms=None,
+             want_phases: bool = False):
+    """maps float64 [ntrans][ncomp][npix] -> alm [ntrans][ncomp][nalm][2]
+    (only the m in ``ms`` are filled when a subset is given).  ``weight``
+    overrides the geometry's ring weights (ones = adjoint synthesis).
+    With want_phases also returns G [ntrans][ncomp][nrings][mmax+1][2]."""
+    th, nph, p0, w, ofs = _geom_arrays(geom)
+    if weight is not None:
+        w = np.ascontiguousarray(np.broadcast_to(weight, th.shape), dtype=np.float64)
+    maps = np.ascontiguousarray(maps, dtype=np.float64)
+    ntrans, ncomp = maps.shape[0], maps.shape[1]
+    n = (mmax + 1) * (lmax + 1) - (mmax * (mmax + 1)) // 2
+    alm = np.zeros((ntrans, ncomp, n, 2))
+    G = np.zeros((ntrans, ncomp, geom.nrings, mmax + 1, 2)) if want_phases else None
+    sel = None if ms is None else np.ascontiguousarray(ms, dtype=np.int32)
+    nsel = 0 if sel is None else int(sel.shape[0])
+    rc = _load().oracle_analysis(geom.nrings, _ptr(th, _dp), _ptr(nph, _i64p), _ptr(p0, _dp),
+                                 _ptr(w, _dp), _ptr(ofs, _i64p), int(geom.stride), lmax, mmax,
+                                 spin, ntrans, _ptr(maps, _dp), _ptr(alm, _dp), nsel,
+                                 _ptr(sel, _ip), _ptr(G, _dp))
+    if rc:
+        raise RuntimeError(f"oracle_analysis rc={rc}")
+    return (alm, G) if want_phases else alm
+
+
+def adjoint_synthesis(geom, lmax: int, mmax: int, spin: int, maps: np.ndarray, ms=None):
+    """Y^T applied to maps: the analysis sums with all weights equal to one."""
+    return analysis(geom, lmax, mmax, spin, maps, weight=1.0, ms=ms)

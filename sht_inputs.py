@@ -1,0 +1,230 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds no transform arithmetic: it only builds grid geometries
+(ring colatitudes, pixel counts, azimuth offsets, quadrature weights) and
+draws random coefficient sets and maps.  Both the CPU reference in
+``oracle/`` and the GPU library consume what it returns.
+
+Grids
+-----
+* Gauss-Legendre: ``nrings`` rings at the roots of P_nrings(cos theta), equal
+  pixel counts.  Weights follow Eq. 2 of the paper: w_y includes the
+  2 pi / Nphi_y factor, i.e. w_y = w_GL,y * 2 pi / Nphi_y.  South rings are
+  built as pi - theta_north so that ring pairs are exact mirrors.
+* HEALPix (Gorski et al. 2005) ring scheme: 4 Nside - 1 rings; polar caps with
+  4i pixels, the equatorial belt with 4 Nside pixels; uniform weights
+  4 pi / Npix (no iteration).
+
+Coefficients
+------------
+a_lm with E|a_lm|^2 = C_l: for m > 0 Re and Im are N(0, C_l/2), for m = 0 the
+coefficient is real N(0, C_l).  ``powerlaw`` uses C_l = 1/(l+1)^2; ``unit``
+draws Re and Im from N(0, 1) (Im = 0 at m = 0).  Spin-2 sets are zero for
+l < 2.  Seeds: numpy ``default_rng([13034945, tag, transform, component])``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED_ROOT = 13034945
+
+
+@dataclasses.dataclass
+class Geometry:
+    theta: np.ndarray          # float64 [nrings]
+    nphi: np.ndarray           # int64 [nrings]
+    phi0: np.ndarray           # float64 [nrings]
+    weight: np.ndarray         # float64 [nrings], includes 2 pi / nphi
+    ofs: np.ndarray            # int64 [nrings], first pixel of each ring
+    stride: int = 1
+
+    @property
+    def nrings(self) -> int:
+        return int(self.theta.shape[0])
+
+    @property
+    def npix(self) -> int:
+        return int(np.max(self.ofs + (self.nphi - 1) * self.stride) + 1)
+
+    def subset(self, rings) -> "Geometry":
+        """Geometry restricted to the given ring indices (pixel offsets kept)."""
+        rings = np.asarray(rings, dtype=np.int64)
+        return Geometry(self.theta[rings].copy(), self.nphi[rings].copy(),
+                        self.phi0[rings].copy(), self.weight[rings].copy(),
+                        self.ofs[rings].copy(), self.stride)
+
+
+def _packed_offsets(nphi: np.ndarray) -> np.ndarray:
+    ofs = np.zeros_like(nphi)
+    ofs[1:] = np.cumsum(nphi)[:-1]
+    return ofs
+
+
+def _gauss_legendre_theta(n: int):
+    """Gauss-Legendre nodes as colatitudes (ascending) and their weights, by
+    Newton's method on P_n(cos theta) in long double (numpy's leggauss loses
+    ~1e-14 in the weights at n ~ 100, enough to spoil a 1e-12 round trip)."""
+    ld = np.longdouble
+    k = np.arange(1, n + 1).astype(ld)
+    th = (ld(np.pi) * (4 * k - 1) / (4 * n + 2)).astype(ld)
+
+    def legendre(c):
+        p0 = np.ones_like(c)
+        p1 = c.copy()
+        for j in range(2, n + 1):
+            p0, p1 = p1, ((2 * j - 1) * c * p1 - (j - 1) * p0) / j
+        if n == 1:
+            p0, p1 = np.ones_like(c), c
+        dp = n * (c * p1 - p0) / (c * c - 1)
+        return p1, dp
+
+    for _ in range(12):
+        c = np.cos(th)
+        p, dp = legendre(c)
+        step = p / (-np.sin(th) * dp)
+        th = th - step
+        if np.max(np.abs(step)) < 1e-17:     # quadratic convergence: done
+            break
+    c = np.cos(th)
+    _, dp = legendre(c)
+    w = 2 / ((1 - c * c) * dp * dp)
+    return th, w
+
+
+def gauss_geometry(nrings: int, nphi: int, phi0: float = 0.0) -> Geometry:
+    """Gauss-Legendre rings ordered north to south."""
+    thl, wl = _gauss_legendre_theta(nrings)
+    order = np.argsort(thl)
+    theta = thl[order].astype(np.float64)
+    w = wl[order].astype(np.float64)
+    nh = nrings // 2
+    # exact mirror pairs: south = pi - north; symmetric weights
+    for i in range(nh):
+        j = nrings - 1 - i
+        theta[j] = math.pi - theta[i]
+        w[j] = w[i]
+    if nrings % 2 == 1:
+        theta[nh] = 0.5 * math.pi
+    nph = np.full(nrings, nphi, dtype=np.int64)
+    weight = w * (2.0 * math.pi / nph)
+    return Geometry(theta, nph, np.full(nrings, float(phi0)), weight,
+                    _packed_offsets(nph))
+
+
+def healpix_geometry(nside: int) -> Geometry:
+    """HEALPix ring-scheme geometry (pixel order within a ring as in HEALPix)."""
+    nr = 4 * nside - 1
+    theta = np.zeros(nr)
+    nph = np.zeros(nr, dtype=np.int64)
+    phi0 = np.zeros(nr)
+    for i in range(1, 2 * nside + 1):           # north cap + north belt + equator
+        y = i - 1
+        if i < nside:
+            theta[y] = 2.0 * math.asin(i / (math.sqrt(6.0) * nside))
+            nph[y] = 4 * i
+            phi0[y] = math.pi / (4.0 * i)
+        else:
+            z = (4.0 / 3.0) - 2.0 * i / (3.0 * nside)
+            theta[y] = math.acos(z)
+            nph[y] = 4 * nside
+            s = (i - nside + 1) % 2
+            phi0[y] = (math.pi / (2.0 * nside)) * (1.0 - 0.5 * s)
+    for y in range(2 * nside, nr):              # south: mirrors of the north
+        yn = nr - 1 - y
+        theta[y] = math.pi - theta[yn]
+        nph[y] = nph[yn]
+        phi0[y] = phi0[yn]
+    theta[2 * nside - 1] = 0.5 * math.pi
+    npix = 12 * nside * nside
+    weight = np.full(nr, 4.0 * math.pi / npix)
+    return Geometry(theta, nph, phi0, weight, _packed_offsets(nph))
+
+
+def nalm(lmax: int, mmax: int) -> int:
+    return (mmax + 1) * (lmax + 1) - (mmax * (mmax + 1)) // 2
+
+
+def alm_index(lmax: int, l, m):
+    return m * (2 * lmax + 1 - m) // 2 + l
+
+
+def lm_arrays(lmax: int, mmax: int):
+    """(l, m) of every stored coefficient, in storage order."""
+    ls, ms = [], []
+    for m in range(mmax + 1):
+        ls.append(np.arange(m, lmax + 1))
+        ms.append(np.full(lmax + 1 - m, m))
+    return np.concatenate(ls), np.concatenate(ms)
+
+
+def random_alm(lmax: int, mmax: int, ntrans: int = 1, spin: int = 0,
+               spectrum: str = "powerlaw", tag: int = 0) -> np.ndarray:
+    """Complex coefficient sets as float64 [ntrans][ncomp][nalm][2]."""
+    ncomp = 2 if spin else 1
+    ls, ms = lm_arrays(lmax, mmax)
+    n = ls.shape[0]
+    out = np.zeros((ntrans, ncomp, n, 2))
+    for t in range(ntrans):
+        for c in range(ncomp):
+            rng = np.random.default_rng([SEED_ROOT, tag, t, c])
+            re = rng.standard_normal(n)
+            im = rng.standard_normal(n)
+            if spectrum == "unit":
+                sd_re = np.ones(n)
+                sd_im = np.ones(n)
+            elif spectrum == "powerlaw":
+                cl = 1.0 / (ls + 1.0) ** 2
+                sd_re = np.where(ms == 0, np.sqrt(cl), np.sqrt(cl / 2.0))
+                sd_im = np.sqrt(cl / 2.0)
+            else:
+                raise ValueError(spectrum)
+            out[t, c, :, 0] = re * sd_re
+            out[t, c, :, 1] = np.where(ms == 0, 0.0, im * sd_im)
+            if spin:
+                out[t, c, ls < spin, :] = 0.0
+    return out
+
+
+def random_map(geom: Geometry, ntrans: int = 1, ncomp: int = 1, sigma: float = 1.0,
+               tag: int = 0) -> np.ndarray:
+    """White-noise maps float64 [ntrans][ncomp][npix]."""
+    out = np.zeros((ntrans, ncomp, geom.npix))
+    for t in range(ntrans):
+        for c in range(ncomp):
+            rng = np.random.default_rng([SEED_ROOT, 1000 + tag, t, c])
+            out[t, c] = sigma * rng.standard_normal(geom.npix)
+    return out
+
+
+# The five workloads: (name, geometry builder, lmax, spin, ntrans)
+WORKLOADS = {
+    "gl127": dict(desc="GL 128 rings x 255 px, lmax=mmax=127, spin 0, 1 transform, "
+                       "Re/Im ~ N(0,1)", grid=("gauss", 128, 255), lmax=127, spin=0,
+                  ntrans=1, spectrum="unit"),
+    "hp1024": dict(desc="HEALPix Nside=1024, lmax=mmax=2047, spin 0, 1 transform, "
+                        "C_l=1/(l+1)^2", grid=("healpix", 1024), lmax=2047, spin=0,
+                   ntrans=1, spectrum="powerlaw"),
+    "gl4095s2": dict(desc="GL 4096 rings x 8191 px, lmax=mmax=4095, spin 2 (E/B<->Q/U), "
+                          "16 transforms, C_l=1/(l+1)^2", grid=("gauss", 4096, 8191),
+                     lmax=4095, spin=2, ntrans=16, spectrum="powerlaw"),
+    "hp2048": dict(desc="HEALPix Nside=2048, lmax=mmax=4095, spin 0, 8 maps",
+                   grid=("healpix", 2048), lmax=4095, spin=0, ntrans=8,
+                   spectrum="powerlaw"),
+}
+
+
+def make_geometry(grid) -> Geometry:
+    if grid[0] == "gauss":
+        return gauss_geometry(grid[1], grid[2])
+    if grid[0] == "healpix":
+        return healpix_geometry(grid[1])
+    raise ValueError(grid)
+
+
+def mixed_batch_lmaxes():
+    """The mixed batch: 16 transforms each at lmax 255, 511, 1023, 2047 on
+    Gauss-Legendre grids with lmax+1 rings and 2 lmax + 1 pixels per ring."""
+    return [255, 511, 1023, 2047]
