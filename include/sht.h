@@ -1,0 +1,176 @@
+/*
+ * sht.h -- C ABI of libsht, spherical harmonic transforms on AMD MI355X (gfx950).
+ *
+ * The operations follow Sect. 2 of Reinecke & Seljebotn (2013), "Libsharp --
+ * spherical harmonic transforms revisited":
+ *
+ *   synthesis (alm2map, Eq. 1):  p_xy = sum_m sum_l a_lm lambda_lm(theta_y)
+ *                                       exp(i m phi0_y + 2 pi i m x / Nphi_y)
+ *   analysis  (map2alm, Eq. 2):  a_lm = sum_y sum_x p_xy w_y lambda_lm(theta_y)
+ *                                       exp(-i m phi0_y - 2 pi i m x / Nphi_y)
+ *   adjoint synthesis (Sect. 4.5, Eq. 16 with W = 1): the analysis sums with
+ *                                 every weight equal to one (Y^T).
+ *
+ * Both are split into a Legendre step (Eqs. 4, 5: the phases F_{m,y}, G_{m,y})
+ * and per-ring real FFTs (Eqs. 3, 6).  Spin 0 and spin 2 are supported
+ * (Sect. 4.1); several transforms of identical type run together (Sect. 3.2).
+ *
+ * Conventions
+ *   - real fields: only m >= 0 is stored, a_{l,-m} = (-1)^m conj(a_lm);
+ *     Im(a_l0) is ignored on input and returned as 0; coefficients with
+ *     l < |spin| are ignored on input and returned as 0;
+ *   - spin 2 takes E/B coefficients and Q/U maps with
+ *     -+2 a_lm = -(E_lm +- i B_lm) and Q +- iU = sum_lm +-2 a_lm +-2 Y_lm;
+ *   - the ring weights w_y of Eq. 2 include the 2 pi / Nphi_y factor
+ *     (Gauss-Legendre: w_GL * 2 pi / Nphi; HEALPix: 4 pi / Npix).
+ *
+ * Layouts (double precision; complex numbers as interleaved (re, im) pairs,
+ * never C99 complex, see Sect. 3.1):
+ *   a_lm   double[ntrans][ncomp][nalm][2], index(l, m) = m(2 lmax + 1 - m)/2 + l
+ *   maps   double[ntrans][ncomp][npix], pixel x of ring y at ofs[y] + x*stride
+ *   phases double[ntrans][ncomp][nrings][mmax + 1][2]  (F for synthesis, G for
+ *          analysis; ring index = the geometry's ring order)
+ *   ncomp is 1 for spin 0 and 2 for spin 2 (E,B resp. Q,U).
+ *
+ * Memory and ownership
+ *   - every data pointer passed to sht_execute / sht_legendre / sht_ring_fft
+ *     is DEVICE memory owned by the caller; it is only borrowed for the
+ *     stream-ordered work and must stay valid until that work completes;
+ *   - geometry, plan and batch objects are owned by the library and freed by
+ *     their destroy functions; a plan owns its device tables and its phase
+ *     workspace (ntrans * ncomp * nrings * (mmax+1) * 16 bytes);
+ *   - a plan (or batch) must not be executed on two streams at once.
+ *
+ * Errors
+ *   Every function returns an sht_status (0 = SHT_OK) and never aborts or
+ *   exits.  Arguments are validated on the host before any GPU work is
+ *   queued.  The message of the last failure on the calling thread is
+ *   available from sht_last_error().  Asynchronous device failures are
+ *   reported as SHT_EDEVICE by a later call.
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SHT_OK = 0,
+    SHT_EINVAL = 1,        /* invalid argument */
+    SHT_ENOMEM = 2,        /* host or device allocation failed */
+    SHT_EDEVICE = 3,       /* no usable gfx950 device, or a HIP call failed */
+    SHT_EUNSUPPORTED = 4,  /* valid request that this library does not implement */
+    SHT_ESTATE = 5         /* object destroyed, corrupted, or in use */
+} sht_status;
+
+enum { SHT_FP64 = 0, SHT_FP32_MFMA = 1 };
+enum { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1, SHT_ALM2MAP_ADJOINT = 2 };
+
+typedef struct sht_geom sht_geom;
+typedef struct sht_plan sht_plan;
+typedef struct sht_batch sht_batch;
+
+/* Plan options; zero-initialise and set what is needed (NULL = defaults). */
+typedef struct sht_plan_opts {
+    int no_polar_skip;     /* 1: evaluate every (m, ring) term (Sect. 3.3 off) */
+    double polar_T;        /* >0: override T of Eq. 8 (default max(100, 0.01 lmax)) */
+    int rescale_bits;      /* >0: exponent step S of the extended-range recursion
+                              (default 256; valid 64..700) */
+    int flush_chunks;      /* FP32_MFMA: FP32 partial sums are carried into FP64
+                              after this many 16-degree chunks (default 1) */
+    int reserved[8];
+} sht_plan_opts;
+
+/* ---- geometry (Sect. 2, Sect. 4.4) ---- */
+
+/* Arbitrary iso-latitude grid.  theta in [0, pi]; nphi >= 1; phi0: azimuth of
+   the first pixel of each ring; weight: w_y of Eq. 2 (may be NULL: analysis
+   is then unavailable, adjoint synthesis still works); ofs: first pixel index
+   of each ring (NULL: rings stored back to back in the given order);
+   stride: distance between neighbouring pixels of a ring (>= 1).
+   All arrays are host memory of length nrings and are copied. */
+int sht_geom_create(int nrings, const double *theta, const int64_t *nphi,
+                    const double *phi0, const double *weight, const int64_t *ofs,
+                    int64_t stride, sht_geom **out);
+/* Gauss-Legendre grid: nrings rings at the roots of P_nrings(cos theta),
+   north to south, nphi pixels each, weights w_GL * 2 pi / nphi. */
+int sht_geom_gauss(int nrings, int64_t nphi, double phi0, sht_geom **out);
+/* HEALPix ring-scheme grid (4 nside - 1 rings, 12 nside^2 pixels), uniform
+   weights 4 pi / Npix. */
+int sht_geom_healpix(int nside, sht_geom **out);
+/* Number of rings and of map pixels (max pixel index + 1). */
+int sht_geom_info(const sht_geom *g, int *nrings, int64_t *npix);
+/* Copy the ring tables out (any pointer may be NULL). */
+int sht_geom_rings(const sht_geom *g, double *theta, int64_t *nphi, double *phi0,
+                   double *weight, int64_t *ofs);
+void sht_geom_destroy(sht_geom *g);
+
+/* ---- a_lm indexing (m-major triangle, Sect. 2) ---- */
+int64_t sht_alm_index(int lmax, int l, int m);   /* m(2 lmax + 1 - m)/2 + l */
+int64_t sht_nalm(int lmax, int mmax);            /* number of stored a_lm */
+
+/* ---- plans ---- */
+
+/* A plan binds a geometry (copied), band limits lmax >= mmax >= 0, spin (0 or 2;
+   spin <= lmax), the number of simultaneous transforms ntrans >= 1 (Sect. 3.2)
+   and the arithmetic of the Legendre step (SHT_FP64, or SHT_FP32_MFMA: FP64
+   recursion, FP32 matrix-core products with FP64 carry).  Uses the current
+   HIP device. */
+int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans,
+                    int precision, const sht_plan_opts *opts, sht_plan **out);
+void sht_plan_destroy(sht_plan *p);
+
+/* Full transform, stream-ordered on hip_stream (a hipStream_t; NULL = null stream).
+   SHT_ALM2MAP: in = a_lm, out = maps.  SHT_MAP2ALM: in = maps, out = a_lm
+   (needs weights).  SHT_ALM2MAP_ADJOINT: in = maps, out = Y^T maps.
+   in and out must not overlap. */
+int sht_execute(sht_plan *p, int direction, const double *in, double *out,
+                void *hip_stream);
+
+/* Legendre step only (Eqs. 4, 5).  SHT_ALM2MAP: in = a_lm, out = F phases.
+   SHT_MAP2ALM / SHT_ALM2MAP_ADJOINT: in = G phases, out = a_lm. */
+int sht_legendre(sht_plan *p, int direction, const double *in, double *out,
+                 void *hip_stream);
+
+/* Ring FFT step only (Eqs. 3, 6).  SHT_ALM2MAP: in = F phases, out = maps.
+   SHT_MAP2ALM: in = maps, out = G phases with weights w_y;
+   SHT_ALM2MAP_ADJOINT: the same with all weights one. */
+int sht_ring_fft(sht_plan *p, int direction, const double *in, double *out,
+                 void *hip_stream);
+
+/* Algorithmic work of one Legendre step in the given direction after polar
+   skipping: floating-point operations (the recursion counted once per ring
+   slot and degree, the products per transform) and the minimal HBM bytes of
+   a whole transform (inputs, phases written and read once, outputs). */
+int sht_plan_flops(const sht_plan *p, int direction, double *flops, double *hbm_bytes);
+
+/* Kernel-level statistics of the last sht_execute on this plan: number of
+   Legendre work items and of ring FFT work items (for reports). */
+int sht_plan_info(const sht_plan *p, int64_t *n_legendre_items, int64_t *workspace_bytes);
+
+/* ---- batches of plans (mixed band limits and grids) ---- */
+
+/* A batch runs several plans (same spin and direction per call) as one
+   stream-ordered unit: the Legendre work of every plan is merged into one
+   cost-ordered persistent launch, the ring FFTs into one launch.  The plans
+   are borrowed and must outlive the batch. */
+int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out);
+int sht_batch_execute(sht_batch *b, int direction, const double *const *in,
+                      double *const *out, void *hip_stream);
+void sht_batch_destroy(sht_batch *b);
+
+/* Pick tile parameters for a plan by timing candidates on scratch data for
+   about budget_seconds (Sect. 3.2); results are cached in the file named by
+   $SHT_TUNE_CACHE (if set). */
+int sht_autotune(sht_plan *p, double budget_seconds);
+
+const char *sht_last_error(void);
+const char *sht_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHT_H */

@@ -1,0 +1,927 @@
+// Per-ring FFTs of the paper's Eqs. 3 and 6 on gfx950.
+//
+// Synthesis (Eq. 3), per ring y: c_m = F_{m,y} e^{i m phi0_y} for |m| <= mmax
+// (c_{-m} = conj c_m), aliased onto the Nphi_y bins b_k = sum_{m = k mod Nphi} c_m,
+// then p_x = sum_k b_k e^{2 pi i k x / Nphi} (an unnormalised inverse real DFT).
+// Analysis (Eq. 6): G_{m,y} = w_y e^{-i m phi0} sum_x p_x e^{-2 pi i m x / Nphi}.
+//
+// Each work item is one complex FFT held in LDS:
+//   * even Nphi: one ring, the standard half-length packing z_n = x_2n + i x_2n+1;
+//   * odd Nphi:  two rings of equal length (a ring and its mirror) packed as
+//     z = a + i b.
+// A complex length L that factors into 2,3,5,7,11,13 is done by an in-place
+// mixed-radix transform (decimation in frequency: natural -> digit-reversed
+// order; decimation in time: digit-reversed -> natural), the spectrum being
+// read or written at digit-reversed positions so that no permutation pass is
+// needed.  Other lengths use Bluestein's chirp transform with a power-of-two
+// inner length M (>= 2L-1); when M complex doubles exceed the LDS, the inner
+// transform is split by one radix-2 step into two halves processed one after
+// the other, the first half's result being kept in registers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "sht_internal.h"
+
+namespace sht {
+
+constexpr int FFT_MAXRAD = 16;
+
+enum { FFT_DIRECT = 0, FFT_BLUE = 1, FFT_BLUE_SPLIT = 2 };
+enum { ROW_PAIR = 0, ROW_HALF = 1 };
+
+struct FftInner {       // an in-LDS complex FFT of length n
+    int n;
+    int nrad;
+    int rad[FFT_MAXRAD];
+    int64_t tw;         // offset of e^{-2 pi i j / n}, j < n
+    int64_t pos;        // offset of pos_of_freq[f], f < n
+};
+
+struct FftLen {         // complex transform of length L
+    int L;
+    int kind;
+    int M;              // Bluestein inner length (full M, also in split mode)
+    int inner;          // index of the FftInner used (length L, M or M/2)
+    int64_t chirp;      // L entries e^{+i pi n^2 / L}
+    int64_t bhat_p;     // kernel spectrum for sign +  (M entries; split: even half then odd half)
+    int64_t bhat_m;     // kernel spectrum for sign -
+    int64_t wm;         // split: e^{-2 pi i n / M}, n < M/2
+    int lds_complex;    // LDS buffer size in complex elements
+};
+
+struct FftRow {
+    int mode;           // ROW_PAIR or ROW_HALF
+    int ya, yb;         // rings (yb = -1: none)
+    int len;            // FftLen index
+    int nphi;
+    int64_t half_tw;    // ROW_HALF: e^{-2 pi i k / nphi}, k < nphi/2
+};
+
+struct FftView {
+    const FftInner *inner;
+    const FftLen *lens;
+    const FftRow *rows;
+    const double2 *ctab;     // complex tables
+    const int *itab;         // integer tables
+    const int64_t *ofs;      // ring pixel offsets
+    int64_t stride;
+    const double *weight;
+    const double2 *rot;      // per ring: 64 fine + ncoarse coarse rotations e^{i m phi0}
+    int nrot;                // entries per ring
+    const int *mvalid;       // per ring: largest meaningful m
+    int mmax, nrings, ncomp;
+    int64_t npix;
+};
+
+// ------------------------------------------------------------------ device
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by -i (fwd = true) or +i
+__device__ __forceinline__ double2 cmul_mi(double2 a, bool fwd)
+{
+    return fwd ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+}
+
+// small DFT out_k = sum_j v_j w_r^{jk}, w_r = e^{-2 pi i / r} (fwd) or conjugate.
+template <int R>
+__device__ __forceinline__ void small_dft(double2 *v, bool fwd, const double2 *tw, int n)
+{
+    if constexpr (R == 2) {
+        double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        double2 c = cadd(v[1], v[3]), d = cmul_mi(csub(v[1], v[3]), fwd);
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, d);
+        v[3] = csub(b, d);
+    } else if constexpr (R == 8) {
+        // two radix-4 DFTs over even/odd inputs, then a radix-2 combination
+        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        small_dft<4>(e, fwd, tw, n);
+        small_dft<4>(o, fwd, tw, n);
+        const double h = 0.70710678118654752440;
+        // o[k] *= w8^k
+        o[1] = fwd ? make_double2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x))
+                   : make_double2(h * (o[1].x - o[1].y), h * (o[1].y + o[1].x));
+        o[2] = cmul_mi(o[2], fwd);
+        o[3] = fwd ? make_double2(h * (-o[3].x + o[3].y), h * (-o[3].y - o[3].x))
+                   : make_double2(h * (-o[3].x - o[3].y), h * (-o[3].y + o[3].x));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
+    } else {
+        // generic odd radix: roots from the length-n table (n divisible by R)
+        double2 w[R];
+        const int step = n / R;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            double2 t = tw[j * step];
+            w[j] = fwd ? t : cconj(t);
+        }
+        double2 out[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            double2 s = v[0];
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                const double2 ww = w[(j * k) % R];
+                s.x += v[j].x * ww.x - v[j].y * ww.y;
+                s.y += v[j].x * ww.y + v[j].y * ww.x;
+            }
+            out[k] = s;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = out[k];
+    }
+}
+
+// one pass over the block of length Lb split by radix R (stride Ln = Lb / R)
+template <int R, bool DIT>
+__device__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
+{
+    const int Ln = Lb / R;
+    const int nb = n / R;
+    const int tstep = n / Lb;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        const int b = q / Ln;
+        const int n1 = q - b * Ln;
+        const int base = b * Lb + n1;
+        double2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = buf[base + j * Ln];
+        if constexpr (DIT) {
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                double2 t = tw[tstep * n1 * j];
+                v[j] = cmul(v[j], fwd ? t : cconj(t));
+            }
+            small_dft<R>(v, fwd, tw, n);
+        } else {
+            small_dft<R>(v, fwd, tw, n);
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                double2 t = tw[tstep * n1 * j];
+                v[j] = cmul(v[j], fwd ? t : cconj(t));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) buf[base + j * Ln] = v[j];
+    }
+    __syncthreads();
+}
+
+template <bool DIT>
+__device__ void fft_pass_any(double2 *buf, int n, int Lb, int r, bool fwd, const double2 *tw)
+{
+    switch (r) {
+    case 2: fft_pass<2, DIT>(buf, n, Lb, fwd, tw); break;
+    case 3: fft_pass<3, DIT>(buf, n, Lb, fwd, tw); break;
+    case 4: fft_pass<4, DIT>(buf, n, Lb, fwd, tw); break;
+    case 5: fft_pass<5, DIT>(buf, n, Lb, fwd, tw); break;
+    case 7: fft_pass<7, DIT>(buf, n, Lb, fwd, tw); break;
+    case 8: fft_pass<8, DIT>(buf, n, Lb, fwd, tw); break;
+    case 11: fft_pass<11, DIT>(buf, n, Lb, fwd, tw); break;
+    case 13: fft_pass<13, DIT>(buf, n, Lb, fwd, tw); break;
+    default: break;
+    }
+}
+
+// natural order in, digit-reversed out
+__device__ void fft_dif(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
+{
+    const double2 *tw = ctab + in.tw;
+    int Lb = in.n;
+    for (int i = 0; i < in.nrad; ++i) {
+        fft_pass_any<false>(buf, in.n, Lb, in.rad[i], fwd, tw);
+        Lb /= in.rad[i];
+    }
+}
+
+// digit-reversed in, natural order out
+__device__ void fft_dit(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
+{
+    const double2 *tw = ctab + in.tw;
+    int Lb = 1;
+    for (int i = in.nrad - 1; i >= 0; --i) {
+        Lb *= in.rad[i];
+        fft_pass_any<true>(buf, in.n, Lb, in.rad[i], fwd, tw);
+    }
+}
+
+// Complex DFT of length L with sign fwd (e^{-}) or inverse (e^{+}), natural
+// order in and out, for the Bluestein kinds.  buf holds the input x_n, n < L;
+// on return buf holds X_k, k < L.  Uses LDS buf (size lds_complex) and, in
+// split mode, the register arrays of the calling thread (NREG per thread).
+template <int NREG>
+__device__ void bluestein(double2 *buf, const FftView &fv, const FftLen &d, bool fwd)
+{
+    const FftInner &in = fv.inner[d.inner];
+    const double2 *chirp = fv.ctab + d.chirp;
+    const double2 *bh = fv.ctab + (fwd ? d.bhat_m : d.bhat_p);
+    const int L = d.L;
+    // chirp for sign s: w_n = e^{s i pi n^2/L}; table holds s = +
+    auto wch = [&](int n) { double2 c = chirp[n]; return fwd ? cconj(c) : c; };
+    if (d.kind == FFT_BLUE) {
+        const int M = d.M;
+        for (int n = threadIdx.x; n < M; n += blockDim.x) {
+            double2 a = make_double2(0.0, 0.0);
+            if (n < L) a = cmul(buf[n], wch(n));
+            buf[n] = a;
+        }
+        __syncthreads();
+        fft_dif(buf, in, true, fv.ctab);
+        for (int p = threadIdx.x; p < M; p += blockDim.x) buf[p] = cmul(buf[p], bh[p]);
+        __syncthreads();
+        fft_dit(buf, in, false, fv.ctab);
+        for (int k = threadIdx.x; k < L; k += blockDim.x) buf[k] = cmul(buf[k], wch(k));
+        __syncthreads();
+    } else {
+        const int Mh = d.M / 2;
+        const double2 *wm = fv.ctab + d.wm;
+        double2 xr[NREG], er[NREG];
+        // keep the chirped input in registers
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) {
+            const int n = threadIdx.x + j * blockDim.x;
+            xr[j] = (n < L) ? cmul(buf[n], wch(n)) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        // even half: FFT_{M/2}(a), times kernel, inverse
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) {
+            const int n = threadIdx.x + j * blockDim.x;
+            if (n < Mh) buf[n] = xr[j];
+        }
+        __syncthreads();
+        fft_dif(buf, in, true, fv.ctab);
+        for (int p = threadIdx.x; p < Mh; p += blockDim.x) buf[p] = cmul(buf[p], bh[p]);
+        __syncthreads();
+        fft_dit(buf, in, false, fv.ctab);
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) {
+            const int n = threadIdx.x + j * blockDim.x;
+            er[j] = (n < Mh) ? buf[n] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        // odd half: FFT_{M/2}(a_n w_M^n)
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) {
+            const int n = threadIdx.x + j * blockDim.x;
+            if (n < Mh) buf[n] = cmul(xr[j], wm[n]);
+        }
+        __syncthreads();
+        fft_dif(buf, in, true, fv.ctab);
+        for (int p = threadIdx.x; p < Mh; p += blockDim.x) buf[p] = cmul(buf[p], bh[Mh + p]);
+        __syncthreads();
+        fft_dit(buf, in, false, fv.ctab);
+        // c_n = E_n + w_M^{-n} O_n ; X_k = w_k c_k
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) {
+            const int n = threadIdx.x + j * blockDim.x;
+            if (n < L) {
+                double2 c = cadd(er[j], cmul(buf[n], cconj(wm[n])));
+                xr[j] = cmul(c, wch(n));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) {
+            const int n = threadIdx.x + j * blockDim.x;
+            if (n < L) buf[n] = xr[j];
+        }
+        __syncthreads();
+    }
+}
+
+// e^{i m phi0} of ring y for 0 <= m (fine/coarse split by 64)
+__device__ __forceinline__ double2 ring_rot(const FftView &fv, int y, int m)
+{
+    const double2 *r = fv.rot + (int64_t)y * fv.nrot;
+    return cmul(r[m & 63], r[64 + (m >> 6)]);
+}
+
+// Folded Hermitian spectrum bin k of ring y for component row `row`:
+// b_k = sum over m = k mod N, |m| <= mv, of F_m e^{i m phi0} (conjugated for m < 0).
+__device__ double2 fold_bin(const FftView &fv, const double2 *Frow, int y, int N, int mv, int k)
+{
+    double2 s = make_double2(0.0, 0.0);
+    for (int m = k; m <= mv; m += N) s = cadd(s, cmul(Frow[m], ring_rot(fv, y, m)));
+    for (int m = N - k; m <= mv; m += N) {
+        if (m == 0) continue;
+        s = cadd(s, cconj(cmul(Frow[m], ring_rot(fv, y, m))));
+    }
+    return s;
+}
+
+template <int NREG>
+__global__ __launch_bounds__(512) void k_ring_synth(FftView fv, const int *__restrict__ rowlist,
+                                                    const double *__restrict__ phase,
+                                                    double *__restrict__ map)
+{
+    extern __shared__ double2 buf[];
+    const FftRow row = fv.rows[rowlist[blockIdx.x]];
+    const int tc = blockIdx.y;   // transform * ncomp + component
+    const FftLen d = fv.lens[row.len];
+    const FftInner &in = fv.inner[d.inner];
+    const int N = row.nphi;
+    const int64_t rowF = (int64_t)tc * fv.nrings;
+    const double2 *Fa = reinterpret_cast<const double2 *>(phase) + (rowF + row.ya) * (fv.mmax + 1);
+    const int mva = min(fv.mvalid[row.ya], fv.mmax);
+    double *mp = map + (int64_t)tc * fv.npix;
+    const int L = d.L;
+    const bool direct = d.kind == FFT_DIRECT;
+    const int *pos = fv.itab + in.pos;
+
+    if (row.mode == ROW_PAIR) {
+        const double2 *Fb = nullptr;
+        int mvb = -1;
+        if (row.yb >= 0) {
+            Fb = reinterpret_cast<const double2 *>(phase) + (rowF + row.yb) * (fv.mmax + 1);
+            mvb = min(fv.mvalid[row.yb], fv.mmax);
+        }
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            double2 A = fold_bin(fv, Fa, row.ya, N, mva, k);
+            double2 B = make_double2(0.0, 0.0);
+            if (Fb) B = fold_bin(fv, Fb, row.yb, N, mvb, k);
+            double2 Z = make_double2(A.x - B.y, A.y + B.x);   // A + iB
+            buf[direct ? pos[k] : k] = Z;
+        }
+        __syncthreads();
+        if (direct) fft_dit(buf, in, false, fv.ctab);
+        else bluestein<NREG>(buf, fv, d, false);
+        for (int x = threadIdx.x; x < N; x += blockDim.x) {
+            const double2 z = buf[x];
+            mp[fv.ofs[row.ya] + (int64_t)x * fv.stride] = z.x;
+            if (row.yb >= 0) mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] = z.y;
+        }
+    } else {
+        // even N = 2h: Z_k = X_k (1 + i w^k) + conj(X_{h-k}) (1 - i w^k), w = e^{2 pi i/N}
+        const int h = N / 2;
+        const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}
+        for (int k = threadIdx.x; k < h; k += blockDim.x) {
+            double2 X = fold_bin(fv, Fa, row.ya, N, mva, k);
+            double2 Y = cconj(fold_bin(fv, Fa, row.ya, N, mva, h - k));
+            double2 w = cconj(htw[k]);
+            double2 iw = make_double2(-w.y, w.x);
+            double2 Z = cadd(cadd(X, cmul(X, iw)), csub(Y, cmul(Y, iw)));
+            buf[direct ? pos[k] : k] = Z;
+        }
+        __syncthreads();
+        if (direct) fft_dit(buf, in, false, fv.ctab);
+        else bluestein<NREG>(buf, fv, d, false);
+        for (int n = threadIdx.x; n < h; n += blockDim.x) {
+            const double2 z = buf[n];
+            mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride] = z.x;
+            mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride] = z.y;
+        }
+    }
+    (void)L;
+}
+
+template <int NREG>
+__global__ __launch_bounds__(512) void k_ring_anal(FftView fv, const int *__restrict__ rowlist,
+                                                   const double *__restrict__ map,
+                                                   double *__restrict__ phase, int use_weights)
+{
+    extern __shared__ double2 buf[];
+    const FftRow row = fv.rows[rowlist[blockIdx.x]];
+    const int tc = blockIdx.y;
+    const FftLen d = fv.lens[row.len];
+    const FftInner &in = fv.inner[d.inner];
+    const int N = row.nphi;
+    const int64_t rowF = (int64_t)tc * fv.nrings;
+    const double *mp = map + (int64_t)tc * fv.npix;
+    const bool direct = d.kind == FFT_DIRECT;
+    const int *pos = fv.itab + in.pos;
+    auto rd = [&](int k) { return buf[direct ? pos[k] : k]; };
+
+    if (row.mode == ROW_PAIR) {
+        for (int x = threadIdx.x; x < N; x += blockDim.x) {
+            double a = mp[fv.ofs[row.ya] + (int64_t)x * fv.stride];
+            double b = row.yb >= 0 ? mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] : 0.0;
+            buf[x] = make_double2(a, b);
+        }
+        __syncthreads();
+        if (direct) fft_dif(buf, in, true, fv.ctab);
+        else bluestein<NREG>(buf, fv, d, true);
+        for (int side = 0; side < (row.yb >= 0 ? 2 : 1); ++side) {
+            const int y = side ? row.yb : row.ya;
+            const int mv = min(fv.mvalid[y], fv.mmax);
+            const double w = use_weights ? fv.weight[y] : 1.0;
+            double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
+            for (int m = threadIdx.x; m <= mv; m += blockDim.x) {
+                const int k = m % N;
+                const int kc = (N - k) % N;
+                const double2 Zk = rd(k), Zc = cconj(rd(kc));
+                double2 S;
+                if (!side) S = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
+                else {
+                    // (Zk - Zc) / (2i)
+                    const double2 dd = csub(Zk, Zc);
+                    S = make_double2(0.5 * dd.y, -0.5 * dd.x);
+                }
+                const double2 r = cconj(ring_rot(fv, y, m));
+                const double2 g = cmul(S, r);
+                G[m] = make_double2(w * g.x, w * g.y);
+            }
+        }
+    } else {
+        const int h = N / 2;
+        for (int n = threadIdx.x; n < h; n += blockDim.x) {
+            double a = mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride];
+            double b = mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride];
+            buf[n] = make_double2(a, b);
+        }
+        __syncthreads();
+        if (direct) fft_dif(buf, in, true, fv.ctab);
+        else bluestein<NREG>(buf, fv, d, true);
+        const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}, k < h
+        const int y = row.ya;
+        const int mv = min(fv.mvalid[y], fv.mmax);
+        const double w = use_weights ? fv.weight[y] : 1.0;
+        double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
+        for (int m = threadIdx.x; m <= mv; m += blockDim.x) {
+            int k = m % N;
+            bool cj = false;
+            if (k > h) { k = N - k; cj = true; }     // X_{N-k} = conj X_k
+            // X_k = E_k + e^{-2 pi i k/N} O_k, E/O from Z_k and conj Z_{h-k} (indices mod h)
+            const int k1 = k % h, k2 = (h - k) % h;
+            const double2 Zk = rd(k1), Zc = cconj(rd(k2));
+            const double2 E = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
+            const double2 dd = csub(Zk, Zc);
+            const double2 O = make_double2(0.5 * dd.y, -0.5 * dd.x);
+            double2 tw;
+            if (k < h) tw = htw[k];
+            else tw = make_double2(-1.0, 0.0);     // k == h: e^{-i pi}
+            double2 X = cadd(E, cmul(tw, O));
+            if (cj) X = cconj(X);
+            const double2 r = cconj(ring_rot(fv, y, m));
+            const double2 g = cmul(X, r);
+            G[m] = make_double2(w * g.x, w * g.y);
+        }
+    }
+}
+
+// Bluestein kernel spectra: Bhat = FFT_M(b) / M, b_j = conj(w_j) for |j| < L
+// (w for the given sign), stored in the inner transform's digit-reversed order.
+__global__ __launch_bounds__(512) void k_blue_prep(FftView fv, int len_id, int fwd_sign,
+                                                   double2 *out)
+{
+    extern __shared__ double2 buf[];
+    const FftLen d = fv.lens[len_id];
+    const FftInner &in = fv.inner[d.inner];
+    const double2 *chirp = fv.ctab + d.chirp;
+    const int L = d.L, M = d.M;
+    // b_j for sign s: conj(w_j) with w_j = e^{s i pi j^2/L}; table holds s = +
+    auto bval = [&](int j) -> double2 {
+        int jj = j;
+        if (jj >= M - L + 1 && jj > 0) jj = M - jj;
+        else if (jj >= L) return make_double2(0.0, 0.0);
+        double2 c = chirp[jj];
+        return fwd_sign ? c : cconj(c);   // s = -: conj(conj(c)) = c
+    };
+    const double invM = 1.0 / (double)M;
+    if (d.kind == FFT_BLUE) {
+        for (int j = threadIdx.x; j < M; j += blockDim.x) buf[j] = bval(j);
+        __syncthreads();
+        fft_dif(buf, in, true, fv.ctab);
+        for (int p = threadIdx.x; p < M; p += blockDim.x)
+            out[p] = make_double2(buf[p].x * invM, buf[p].y * invM);
+    } else {
+        const int Mh = M / 2;
+        const double2 *wm = fv.ctab + d.wm;
+        for (int half = 0; half < 2; ++half) {
+            for (int j = threadIdx.x; j < Mh; j += blockDim.x) {
+                double2 a = bval(j), b = bval(j + Mh);
+                buf[j] = half ? cmul(csub(a, b), wm[j]) : cadd(a, b);
+            }
+            __syncthreads();
+            fft_dif(buf, in, true, fv.ctab);
+            for (int p = threadIdx.x; p < Mh; p += blockDim.x)
+                out[half * Mh + p] = make_double2(buf[p].x * invM, buf[p].y * invM);
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+static bool factor_smooth(int n, std::vector<int> &rad)
+{
+    rad.clear();
+    int m = n;
+    while (m % 8 == 0 && m > 8) { rad.push_back(8); m /= 8; }
+    while (m % 4 == 0) { rad.push_back(4); m /= 4; }
+    while (m % 2 == 0) { rad.push_back(2); m /= 2; }
+    const int odd[] = {3, 5, 7, 11, 13};
+    for (int r : odd)
+        while (m % r == 0) { rad.push_back(r); m /= r; }
+    if (m == 8) rad.push_back(8), m = 1;
+    return m == 1 && (int)rad.size() <= FFT_MAXRAD;
+}
+
+struct FftHost {
+    std::vector<double2> ctab;
+    std::vector<int> itab;
+    std::vector<FftInner> inner;
+    std::vector<FftLen> lens;
+    std::vector<FftRow> rows;
+    std::map<int, int> inner_of_n, len_of_L, halftw_of_N;
+};
+
+static const long double kPi = 3.14159265358979323846264338327950288L;
+
+static int add_inner(FftHost &H, int n)
+{
+    auto it = H.inner_of_n.find(n);
+    if (it != H.inner_of_n.end()) return it->second;
+    FftInner in{};
+    in.n = n;
+    std::vector<int> rad;
+    factor_smooth(n, rad);
+    in.nrad = (int)rad.size();
+    for (int i = 0; i < in.nrad; ++i) in.rad[i] = rad[i];
+    in.tw = (int64_t)H.ctab.size();
+    for (int j = 0; j < n; ++j) {
+        long double a = -2.0L * kPi * (long double)j / (long double)n;
+        H.ctab.push_back(make_double2((double)cosl(a), (double)sinl(a)));
+    }
+    // digit-reversed position of each frequency for the DIF pass sequence:
+    // position p = sum_i k_i L_{i+1}, frequency f = k_0 + r_0 (k_1 + r_1 (...))
+    in.pos = (int64_t)H.itab.size();
+    H.itab.resize(H.itab.size() + n);
+    for (int f = 0; f < n; ++f) {
+        int rem = f, p = 0, Lb = n;
+        for (int i = 0; i < in.nrad; ++i) {
+            const int r = in.rad[i];
+            const int k = rem % r;
+            rem /= r;
+            Lb /= r;
+            p += k * Lb;
+        }
+        H.itab[in.pos + f] = p;
+    }
+    int id = (int)H.inner.size();
+    H.inner.push_back(in);
+    H.inner_of_n[n] = id;
+    return id;
+}
+
+static int lds_limit_complex()
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int bytes = 0;
+    if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        bytes = 65536;
+    }
+    int c = 1;
+    while (c * 2 * 16 <= bytes) c *= 2;
+    return c;
+}
+
+static int add_len(FftHost &H, int L, int cmax, int &err)
+{
+    auto it = H.len_of_L.find(L);
+    if (it != H.len_of_L.end()) return it->second;
+    FftLen d{};
+    d.L = L;
+    std::vector<int> rad;
+    if (factor_smooth(L, rad) && L <= cmax) {
+        d.kind = FFT_DIRECT;
+        d.M = L;
+        d.inner = add_inner(H, L);
+        d.lds_complex = L;
+    } else {
+        int M = 1;
+        while (M < 2 * L - 1) M *= 2;
+        d.M = M;
+        if (M <= cmax) {
+            d.kind = FFT_BLUE;
+            d.inner = add_inner(H, M);
+            d.lds_complex = M;
+        } else if (M / 2 <= cmax) {
+            d.kind = FFT_BLUE_SPLIT;
+            d.inner = add_inner(H, M / 2);
+            d.lds_complex = M / 2;
+            d.wm = (int64_t)H.ctab.size();
+            for (int n = 0; n < M / 2; ++n) {
+                long double a = -2.0L * kPi * (long double)n / (long double)M;
+                H.ctab.push_back(make_double2((double)cosl(a), (double)sinl(a)));
+            }
+        } else {
+            err = 1;
+            return -1;
+        }
+        d.chirp = (int64_t)H.ctab.size();
+        for (int n = 0; n < L; ++n) {
+            // e^{+i pi n^2 / L} with n^2 reduced mod 2L
+            long long q = ((long long)n * n) % (2LL * L);
+            long double a = kPi * (long double)q / (long double)L;
+            H.ctab.push_back(make_double2((double)cosl(a), (double)sinl(a)));
+        }
+        d.bhat_p = (int64_t)H.ctab.size();
+        H.ctab.resize(H.ctab.size() + M);
+        d.bhat_m = (int64_t)H.ctab.size();
+        H.ctab.resize(H.ctab.size() + M);
+    }
+    int id = (int)H.lens.size();
+    H.lens.push_back(d);
+    H.len_of_L[L] = id;
+    return id;
+}
+
+static int64_t add_half_tw(FftHost &H, int N)
+{
+    auto it = H.halftw_of_N.find(N);
+    if (it != H.halftw_of_N.end()) return it->second;
+    int64_t o = (int64_t)H.ctab.size();
+    for (int k = 0; k < N / 2; ++k) {
+        long double a = -2.0L * kPi * (long double)k / (long double)N;
+        H.ctab.push_back(make_double2((double)cosl(a), (double)sinl(a)));
+    }
+    H.halftw_of_N[N] = (int)o;
+    return o;
+}
+
+// launch groups: rows sharing LDS size class and register class
+struct FftGroup {
+    int lds_complex;
+    int nreg;      // 0: no split rows; else registers per thread
+    std::vector<int> rows;
+};
+
+struct FftDev {
+    FftInner *inner = nullptr;
+    FftLen *lens = nullptr;
+    FftRow *rows = nullptr;
+    double2 *ctab = nullptr;
+    int *itab = nullptr;
+    int64_t *ofs = nullptr;
+    double *weight = nullptr;
+    double2 *rot = nullptr;
+    int *mvalid = nullptr;
+    int nrot = 0;
+    std::vector<FftGroup> groups;
+    std::vector<int *> group_rows;
+};
+
+}  // namespace sht
+
+namespace sht {
+
+static FftView view_of(const Plan &p, const FftDev &D)
+{
+    FftView v{};
+    v.inner = D.inner;
+    v.lens = D.lens;
+    v.rows = D.rows;
+    v.ctab = D.ctab;
+    v.itab = D.itab;
+    v.ofs = D.ofs;
+    v.stride = p.geom.stride;
+    v.weight = D.weight;
+    v.rot = D.rot;
+    v.nrot = D.nrot;
+    v.mvalid = D.mvalid;
+    v.mmax = p.mmax;
+    v.nrings = p.geom.nrings;
+    v.ncomp = p.ncomp;
+    v.npix = p.geom.npix;
+    return v;
+}
+
+static int nreg_class(int lds_complex, bool split)
+{
+    if (!split) return 0;
+    return (lds_complex + 511) / 512;
+}
+
+int fft_plan_build(Plan &p)
+{
+    const Geom &g = p.geom;
+    FftHost H;
+    const int cmax = lds_limit_complex();
+    int err = 0;
+    // rows: even nphi -> half rows; odd nphi -> pairs of mirror rings of equal length
+    std::vector<int> done(g.nrings, 0);
+    for (const SlotHost &s : p.slots) {
+        const int ya = s.yn, yb = s.ys;
+        if (yb >= 0 && g.nphi[ya] == g.nphi[yb] && (g.nphi[ya] & 1)) {
+            FftRow r{};
+            r.mode = ROW_PAIR;
+            r.ya = ya;
+            r.yb = yb;
+            r.nphi = (int)g.nphi[ya];
+            r.len = add_len(H, r.nphi, cmax, err);
+            H.rows.push_back(r);
+            done[ya] = done[yb] = 1;
+        }
+    }
+    for (int y = 0; y < g.nrings; ++y) {
+        if (done[y]) continue;
+        FftRow r{};
+        r.ya = y;
+        r.yb = -1;
+        r.nphi = (int)g.nphi[y];
+        if (r.nphi % 2 == 0) {
+            r.mode = ROW_HALF;
+            r.len = add_len(H, r.nphi / 2, cmax, err);
+            r.half_tw = add_half_tw(H, r.nphi);
+        } else {
+            r.mode = ROW_PAIR;
+            r.len = add_len(H, r.nphi, cmax, err);
+        }
+        H.rows.push_back(r);
+    }
+    if (err) {
+        set_error("ring length too large for the LDS FFT (max complex length %d)", cmax);
+        return SHT_EUNSUPPORTED;
+    }
+    // per-ring tables
+    std::vector<int> slot_of_ring(g.nrings, -1);
+    for (int i = 0; i < p.nslots; ++i) {
+        slot_of_ring[p.slots[i].yn] = i;
+        if (p.slots[i].ys >= 0) slot_of_ring[p.slots[i].ys] = i;
+    }
+    std::vector<int> mvalid(g.nrings, -1);
+    for (int y = 0; y < g.nrings; ++y) {
+        int sl = slot_of_ring[y];
+        mvalid[y] = (sl >= 0) ? p.tile_mlim[sl / p.slots_per_tile] : -1;
+    }
+    const int ncoarse = p.mmax / 64 + 1;
+    const int nrot = 64 + ncoarse;
+    std::vector<double2> rot((size_t)g.nrings * nrot);
+    for (int y = 0; y < g.nrings; ++y) {
+        const long double ph = g.phi0[y];
+        for (int j = 0; j < 64; ++j)
+            rot[(size_t)y * nrot + j] = make_double2((double)cosl(j * ph), (double)sinl(j * ph));
+        for (int j = 0; j < ncoarse; ++j)
+            rot[(size_t)y * nrot + 64 + j] =
+                make_double2((double)cosl(64.0L * j * ph), (double)sinl(64.0L * j * ph));
+    }
+    // groups by LDS class
+    std::map<std::pair<int, int>, int> gid;
+    FftDev *D = new FftDev();
+    for (int i = 0; i < (int)H.rows.size(); ++i) {
+        const FftLen &d = H.lens[H.rows[i].len];
+        int c = 256;
+        while (c < d.lds_complex) c *= 2;
+        const int nreg = nreg_class(d.lds_complex, d.kind == FFT_BLUE_SPLIT);
+        auto key = std::make_pair(c, nreg);
+        auto it = gid.find(key);
+        if (it == gid.end()) {
+            gid[key] = (int)D->groups.size();
+            D->groups.push_back(FftGroup{c, nreg, {}});
+            it = gid.find(key);
+        }
+        D->groups[it->second].rows.push_back(i);
+    }
+    for (auto &gr : D->groups)
+        if (gr.nreg > 16) {
+            set_error("split FFT needs %d registers per thread (max 16)", gr.nreg);
+            delete D;
+            return SHT_EUNSUPPORTED;
+        }
+    int rc;
+    auto up = [&](void **dst, const void *src, size_t bytes, const char *what) -> int {
+        int r = dev_alloc(dst, bytes ? bytes : 16, what);
+        if (r) return r;
+        return bytes ? dev_upload(*dst, src, bytes, what) : SHT_OK;
+    };
+    if ((rc = up((void **)&D->inner, H.inner.data(), H.inner.size() * sizeof(FftInner), "fft tables")) ||
+        (rc = up((void **)&D->lens, H.lens.data(), H.lens.size() * sizeof(FftLen), "fft tables")) ||
+        (rc = up((void **)&D->rows, H.rows.data(), H.rows.size() * sizeof(FftRow), "fft tables")) ||
+        (rc = up((void **)&D->ctab, H.ctab.data(), H.ctab.size() * sizeof(double2), "fft tables")) ||
+        (rc = up((void **)&D->itab, H.itab.data(), H.itab.size() * sizeof(int), "fft tables")) ||
+        (rc = up((void **)&D->ofs, g.ofs.data(), g.ofs.size() * sizeof(int64_t), "fft tables")) ||
+        (rc = up((void **)&D->weight, g.weight.data(), g.weight.size() * sizeof(double), "fft tables")) ||
+        (rc = up((void **)&D->rot, rot.data(), rot.size() * sizeof(double2), "fft tables")) ||
+        (rc = up((void **)&D->mvalid, mvalid.data(), mvalid.size() * sizeof(int), "fft tables"))) {
+        p.fft.d_rows = D;
+        return rc;
+    }
+    D->nrot = nrot;
+    for (auto &gr : D->groups) {
+        int *dr = nullptr;
+        if ((rc = up((void **)&dr, gr.rows.data(), gr.rows.size() * sizeof(int), "fft rows"))) {
+            p.fft.d_rows = D;
+            return rc;
+        }
+        D->group_rows.push_back(dr);
+    }
+    p.fft.d_rows = D;
+    p.fft.nrows = (int)H.rows.size();
+    p.fft.table_bytes = H.ctab.size() * sizeof(double2) + H.itab.size() * sizeof(int);
+    // Bluestein kernel spectra on the device
+    FftView v = view_of(p, *D);
+    for (int li = 0; li < (int)H.lens.size(); ++li) {
+        const FftLen &d = H.lens[li];
+        if (d.kind == FFT_DIRECT) continue;
+        const size_t lds = (size_t)d.lds_complex * sizeof(double2);
+        if (lds > 65536)
+            if ((rc = check_hip(hipFuncSetAttribute((const void *)k_blue_prep,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                                "fft LDS attribute")))
+                return rc;
+        hipLaunchKernelGGL(k_blue_prep, dim3(1), dim3(512), lds, 0, v, li, 0, D->ctab + d.bhat_p);
+        hipLaunchKernelGGL(k_blue_prep, dim3(1), dim3(512), lds, 0, v, li, 1, D->ctab + d.bhat_m);
+    }
+    if ((rc = check_hip(hipGetLastError(), "bluestein preparation"))) return rc;
+    if ((rc = check_hip(hipDeviceSynchronize(), "bluestein preparation"))) return rc;
+    return SHT_OK;
+}
+
+void fft_plan_free(FftPlan &f)
+{
+    FftDev *D = reinterpret_cast<FftDev *>(f.d_rows);
+    if (!D) return;
+    dev_free(D->inner); dev_free(D->lens); dev_free(D->rows); dev_free(D->ctab);
+    dev_free(D->itab); dev_free(D->ofs); dev_free(D->weight); dev_free(D->rot);
+    dev_free(D->mvalid);
+    for (int *r : D->group_rows) dev_free(r);
+    delete D;
+    f.d_rows = nullptr;
+}
+
+template <int NREG>
+static int launch_group_synth(const FftView &v, const FftGroup &gr, const int *rows,
+                              const double *phase, double *map, int ntc, hipStream_t s)
+{
+    const size_t lds = (size_t)gr.lds_complex * sizeof(double2);
+    if (lds > 65536) {
+        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_synth<NREG>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                           "fft LDS attribute");
+        if (rc) return rc;
+    }
+    const int nt = gr.lds_complex >= 4096 ? 512 : 256;
+    hipLaunchKernelGGL(k_ring_synth<NREG>, dim3((unsigned)gr.rows.size(), (unsigned)ntc), dim3(nt), lds,
+                       s, v, rows, phase, map);
+    return SHT_OK;
+}
+
+template <int NREG>
+static int launch_group_anal(const FftView &v, const FftGroup &gr, const int *rows, const double *map,
+                             double *phase, int ntc, int usew, hipStream_t s)
+{
+    const size_t lds = (size_t)gr.lds_complex * sizeof(double2);
+    if (lds > 65536) {
+        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_anal<NREG>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                           "fft LDS attribute");
+        if (rc) return rc;
+    }
+    const int nt = gr.lds_complex >= 4096 ? 512 : 256;
+    hipLaunchKernelGGL(k_ring_anal<NREG>, dim3((unsigned)gr.rows.size(), (unsigned)ntc), dim3(nt), lds,
+                       s, v, rows, map, phase, usew);
+    return SHT_OK;
+}
+
+int launch_ring_synth(const Plan &p, const double *phase, double *map, hipStream_t s)
+{
+    const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
+    const FftView v = view_of(p, *D);
+    const int ntc = p.ntrans * p.ncomp;
+    for (size_t i = 0; i < D->groups.size(); ++i) {
+        const FftGroup &gr = D->groups[i];
+        int rc;
+        if (gr.nreg == 0) rc = launch_group_synth<1>(v, gr, D->group_rows[i], phase, map, ntc, s);
+        else rc = launch_group_synth<16>(v, gr, D->group_rows[i], phase, map, ntc, s);
+        if (rc) return rc;
+    }
+    return check_hip(hipGetLastError(), "ring synthesis launch");
+}
+
+int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights, hipStream_t s)
+{
+    const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
+    const FftView v = view_of(p, *D);
+    const int ntc = p.ntrans * p.ncomp;
+    for (size_t i = 0; i < D->groups.size(); ++i) {
+        const FftGroup &gr = D->groups[i];
+        int rc;
+        if (gr.nreg == 0) rc = launch_group_anal<1>(v, gr, D->group_rows[i], map, phase, ntc, use_weights, s);
+        else rc = launch_group_anal<16>(v, gr, D->group_rows[i], map, phase, ntc, use_weights, s);
+        if (rc) return rc;
+    }
+    return check_hip(hipGetLastError(), "ring analysis launch");
+}
+
+}  // namespace sht

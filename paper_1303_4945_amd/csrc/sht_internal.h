@@ -1,0 +1,142 @@
+// Internal declarations of libsht (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sht.h"
+
+namespace sht {
+
+constexpr uint32_t kGeomMagic = 0x53474d31u;   // live geometry
+constexpr uint32_t kPlanMagic = 0x53504c31u;   // live plan
+constexpr uint32_t kBatchMagic = 0x53424331u;  // live batch
+constexpr uint32_t kDeadMagic = 0xdeadbeefu;
+
+void set_error(const char *fmt, ...);
+
+struct Geom {
+    uint32_t magic = kGeomMagic;
+    int nrings = 0;
+    std::vector<double> theta, phi0, weight;
+    std::vector<int64_t> nphi, ofs;
+    int64_t stride = 1;
+    bool has_weight = false;
+    int64_t npix = 0;
+};
+
+// One recurrence chain slot: a ring and (optionally) its mirror ring.
+struct SlotHost {
+    int yn = -1, ys = -1;       // north ring (theta <= pi/2) and its mirror (-1: none)
+    double cth = 0, sth = 0;    // cos/sin theta of the north ring
+    double chalf = 0, shalf = 0;  // cos/sin theta/2
+};
+
+// Legendre work item (device layout): one (m, tile of slots).
+struct LegItem {
+    int m;
+    int tile;
+};
+
+// Per-(m, chain) start value: lambda_{l0} = sign * K * cos(t/2)^p * sin(t/2)^q.
+struct StartCoef {
+    double kmant;   // mantissa of K in [0.5, 1)
+    int kexp;       // binary exponent of K
+    int p, q;       // powers of cos(theta/2), sin(theta/2)
+    int sign;       // +1 / -1
+    int pad;
+};
+
+// Device-side view of one plan for the Legendre kernels.
+struct LegView {
+    int lmax, mmax, spin, ntrans, nrings, nslots, ntiles;
+    int rescale_bits;       // S
+    int thresh_bits;        // T_r: rescale when |mu| >= 2^T_r
+    double polar_T;         // Eq. 8 (<0: no polar skip)
+    const double *slot_cos, *slot_sin, *slot_chalf, *slot_shalf;
+    const int *slot_yn, *slot_ys;
+    const double4 *coef;        // (alpha, beta, f, 0) per (m, l)
+    const int64_t *coef_ofs;    // coef + coef_ofs[m] + l  for l >= l0(m)
+    const StartCoef *start;     // [m][chain] chain 0: +s (or 0), chain 1: -s
+    const int *tile_mlim;       // per tile: largest m with an active slot (-1: none)
+    int64_t nalm;
+};
+
+struct FftRing;  // per-ring FFT descriptor (ringfft.hip)
+
+struct FftPlan {
+    // device tables
+    void *d_rows = nullptr;      // FftRow[]: one entry per FFT work item
+    int nrows = 0;
+    double2 *d_tw = nullptr;     // twiddle tables, all lengths
+    int *d_perm = nullptr;       // digit-reversal permutations
+    double2 *d_blue = nullptr;   // Bluestein chirps and kernel spectra
+    int *d_mvalid = nullptr;     // per ring: largest m whose F/G entry is meaningful
+    double2 *d_phase_rot = nullptr;  // per ring: e^{i m phi0} tables (coarse/fine)
+    size_t table_bytes = 0;
+};
+
+struct Plan {
+    uint32_t magic = kPlanMagic;
+    int device = 0;
+    int lmax = 0, mmax = 0, spin = 0, ntrans = 0, precision = 0, ncomp = 1;
+    Geom geom;
+    sht_plan_opts opts{};
+    double polar_T = 100.0;
+    int rescale_bits = 256;
+    int flush_chunks = 1;
+    int64_t nalm = 0;
+    // slots
+    std::vector<SlotHost> slots;
+    int nslots = 0, ntiles = 0, slots_per_tile = 32;
+    std::vector<int> tile_mlim;
+    // host-side work lists
+    std::vector<LegItem> synth_items;
+    std::vector<int> anal_ms;
+    // device memory
+    double *d_slot_cos = nullptr, *d_slot_sin = nullptr, *d_slot_chalf = nullptr,
+           *d_slot_shalf = nullptr;
+    int *d_slot_yn = nullptr, *d_slot_ys = nullptr;
+    double4 *d_coef = nullptr;
+    int64_t *d_coef_ofs = nullptr;
+    StartCoef *d_start = nullptr;
+    int *d_tile_mlim = nullptr;
+    LegItem *d_synth_items = nullptr;
+    int *d_anal_ms = nullptr;
+    double *d_phase = nullptr;       // F / G workspace
+    int64_t phase_elems = 0;         // complex elements
+    FftPlan fft;
+    double flops_synth = 0, flops_anal = 0, hbm_bytes = 0;
+    int64_t n_items = 0;
+    // tuning
+    int synth_waves = 1;
+};
+
+struct Batch {
+    uint32_t magic = kBatchMagic;
+    std::vector<Plan *> plans;
+};
+
+LegView make_leg_view(const Plan &p);
+
+// Legendre step launchers (legendre.hip)
+int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipStream_t s);
+int launch_legendre_anal(const Plan &p, const double *phase, double *alm, hipStream_t s);
+
+// ring FFT (ringfft.hip)
+int fft_plan_build(Plan &p);
+void fft_plan_free(FftPlan &f);
+int launch_ring_synth(const Plan &p, const double *phase, double *map, hipStream_t s);
+int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights,
+                     hipStream_t s);
+
+// device memory helpers
+int dev_alloc(void **ptr, size_t bytes, const char *what);
+void dev_free(void *ptr);
+int dev_upload(void *dst, const void *src, size_t bytes, const char *what);
+int check_hip(hipError_t e, const char *what);
+
+}  // namespace sht
