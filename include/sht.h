@@ -67,7 +67,7 @@ typedef enum {
 } sht_status;
 
 enum { SHT_FP64 = 0, SHT_FP32_MFMA = 1 };
-enum { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1, SHT_ALM2MAP_ADJOINT = 2 };
+enum { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1, SHT_ALM2MAP_ADJOINT = 2, SHT_ALM2MAP_GRAD = 3 };
 
 typedef struct sht_geom sht_geom;
 typedef struct sht_plan sht_plan;
@@ -126,18 +126,23 @@ void sht_plan_destroy(sht_plan *p);
 /* Full transform, stream-ordered on hip_stream (a hipStream_t; NULL = null stream).
    SHT_ALM2MAP: in = a_lm, out = maps.  SHT_MAP2ALM: in = maps, out = a_lm
    (needs weights).  SHT_ALM2MAP_ADJOINT: in = maps, out = Y^T maps.
+   SHT_ALM2MAP_GRAD: in = dL/dmap of a real loss L, out = dL/dRe a + i dL/dIm a for
+   the stored coefficients (m >= 0), i.e. fac_m Y^T g with fac_0 = 1 and
+   fac_m = 2 for m > 0, because a_{l,-m} = (-1)^m conj(a_lm) enters the map too;
+   entries the synthesis ignores (Im a_l0, l < |spin|) get gradient 0.
    in and out must not overlap. */
 int sht_execute(sht_plan *p, int direction, const double *in, double *out,
                 void *hip_stream);
 
 /* Legendre step only (Eqs. 4, 5).  SHT_ALM2MAP: in = a_lm, out = F phases.
-   SHT_MAP2ALM / SHT_ALM2MAP_ADJOINT: in = G phases, out = a_lm. */
+   SHT_MAP2ALM / SHT_ALM2MAP_ADJOINT / SHT_ALM2MAP_GRAD: in = G phases, out = a_lm
+   (GRAD also applies fac_m). */
 int sht_legendre(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 
 /* Ring FFT step only (Eqs. 3, 6).  SHT_ALM2MAP: in = F phases, out = maps.
    SHT_MAP2ALM: in = maps, out = G phases with weights w_y;
-   SHT_ALM2MAP_ADJOINT: the same with all weights one. */
+   SHT_ALM2MAP_ADJOINT and SHT_ALM2MAP_GRAD: the same with all weights one. */
 int sht_ring_fft(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 

@@ -293,8 +293,8 @@ int oracle_synthesis(int nrings, const double *theta, const int64_t *nphi,
         double *lam = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
         /* ph[t][c][m + mmax]: the Eq. 4 phase of the field (complex) */
         cld *ph = (cld *)calloc((size_t)ntrans * ncomp * (2 * mmax + 1), sizeof(cld));
-        double *ctab = (double *)malloc(sizeof(double) * (size_t)N);
-        double *stab = (double *)malloc(sizeof(double) * (size_t)N);
+        ld *ctab = (ld *)malloc(sizeof(ld) * (size_t)N);
+        ld *stab = (ld *)malloc(sizeof(ld) * (size_t)N);
         if (!lam || !ph || !ctab || !stab) {
 #pragma omp atomic write
             err = -2;
@@ -361,25 +361,29 @@ int oracle_synthesis(int nrings, const double *theta, const int64_t *nphi,
                 }
             }
         }
-        /* direct DFT of Eq. 3 with integer-reduced twiddles */
+        /* direct DFT of Eq. 3 with integer-reduced twiddles:
+           p_x = sum_m (P_m e^{i m phi0}) e^{2 pi i ((m x) mod N) / N} */
         const ld twopi = 2.0L * 3.14159265358979323846264338327950288L;
         for (int64_t k = 0; k < N; ++k) {
-            ctab[k] = (double)cosl(twopi * (ld)k / (ld)N);
-            stab[k] = (double)sinl(twopi * (ld)k / (ld)N);
+            ctab[k] = cosl(twopi * (ld)k / (ld)N);
+            stab[k] = sinl(twopi * (ld)k / (ld)N);
         }
+        cld *pr = (cld *)malloc(sizeof(cld) * (size_t)(2 * mmax + 1));
         for (int t = 0; t < ntrans; ++t) {
             const cld *P = ph + ((size_t)t * ncomp) * (2 * mmax + 1);
+            for (int m = -mmax; m <= mmax; ++m) {
+                ld ang = (ld)m * (ld)phi0[y];
+                cld e0 = { cosl(ang), sinl(ang) };
+                pr[m + mmax] = cmul(P[m + mmax], e0);
+            }
             for (int64_t x = 0; x < N; ++x) {
                 cld acc = { 0.0L, 0.0L };
                 for (int m = -mmax; m <= mmax; ++m) {
                     int64_t k = ((int64_t)m * x) % N;
                     if (k < 0) k += N;
-                    ld ang = (ld)m * (ld)phi0[y];
-                    cld e0 = { cosl(ang), sinl(ang) };
-                    cld e1 = { (ld)ctab[k], (ld)stab[k] };
-                    cld term = cmul(P[m + mmax], cmul(e0, e1));
-                    acc.re += term.re;
-                    acc.im += term.im;
+                    const cld c = pr[m + mmax];
+                    acc.re += c.re * ctab[k] - c.im * stab[k];
+                    acc.im += c.re * stab[k] + c.im * ctab[k];
                 }
                 int64_t pix = ofs[y] + x * stride;
                 if (spin == 0) {
@@ -390,6 +394,7 @@ int oracle_synthesis(int nrings, const double *theta, const int64_t *nphi,
                 }
             }
         }
+        free(pr);
         free(lam); free(ph); free(ctab); free(stab);
     }
     free(fact);
@@ -443,16 +448,23 @@ int oracle_analysis(int nrings, const double *theta, const int64_t *nphi,
             const int64_t N = nphi[y];
             ld ang0 = -(ld)m * (ld)phi0[y];
             cld e0 = { cosl(ang0), sinl(ang0) };
+            /* e^{-2 pi i m x / N} for x = 0..N-1, by the integer-reduced angle */
+            ld *cx = (ld *)malloc(sizeof(ld) * (size_t)N);
+            ld *sx = (ld *)malloc(sizeof(ld) * (size_t)N);
+            for (int64_t x = 0; x < N; ++x) {
+                int64_t k = ((int64_t)m * x) % N;
+                ld a = -twopi * (ld)k / (ld)N;
+                cx[x] = cosl(a);
+                sx[x] = sinl(a);
+            }
             for (int t = 0; t < ntrans; ++t) {
                 for (int c = 0; c < ncomp; ++c) {
                     const double *mp = map + ((size_t)t * ncomp + c) * map_size;
                     cld acc = { 0.0L, 0.0L };
                     for (int64_t x = 0; x < N; ++x) {
-                        int64_t k = ((int64_t)m * x) % N;
-                        ld a = -twopi * (ld)k / (ld)N;
                         ld v = (ld)mp[ofs[y] + x * stride];
-                        acc.re += v * cosl(a);
-                        acc.im += v * sinl(a);
+                        acc.re += v * cx[x];
+                        acc.im += v * sx[x];
                     }
                     acc = cmul(acc, e0);
                     acc.re *= (ld)wgt[y];
@@ -464,6 +476,8 @@ int oracle_analysis(int nrings, const double *theta, const int64_t *nphi,
                     }
                 }
             }
+            free(cx);
+            free(sx);
         }
         if (spin == 0) {
             cld *acc = (cld *)calloc((size_t)ntrans * (lmax + 1), sizeof(cld));

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_EUNSUPPORTED, SHT_ESTATE = range(6)
 FP64, FP32_MFMA = 0, 1
-ALM2MAP, MAP2ALM, ALM2MAP_ADJOINT = 0, 1, 2
+ALM2MAP, MAP2ALM, ALM2MAP_ADJOINT, ALM2MAP_GRAD = 0, 1, 2, 3
 
 _STATUS_NAMES = {1: "SHT_EINVAL", 2: "SHT_ENOMEM", 3: "SHT_EDEVICE", 4: "SHT_EUNSUPPORTED",
                  5: "SHT_ESTATE"}
@@ -226,6 +226,10 @@ class Plan:
     def adjoint(self, maps, stream=None, out=None):
         """Y^T maps (adjoint synthesis: analysis sums with unit weights)."""
         return self._run(_lib.sht_execute, ALM2MAP_ADJOINT, maps, self.alm_shape, stream, out)
+
+    def alm2map_grad(self, grad_maps, stream=None, out=None):
+        """dL/d(Re a) + i dL/d(Im a) of a real loss L from dL/dmap (fac_m Y^T g)."""
+        return self._run(_lib.sht_execute, ALM2MAP_GRAD, grad_maps, self.alm_shape, stream, out)
 
     def legendre_synth(self, alm, stream=None):
         return self._run(_lib.sht_legendre, ALM2MAP, alm, self.phase_shape, stream)

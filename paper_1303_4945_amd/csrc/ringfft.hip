@@ -723,7 +723,7 @@ int fft_plan_build(Plan &p)
     std::vector<int> done(g.nrings, 0);
     for (const SlotHost &s : p.slots) {
         const int ya = s.yn, yb = s.ys;
-        if (yb >= 0 && g.nphi[ya] == g.nphi[yb] && (g.nphi[ya] & 1)) {
+        if (ya >= 0 && yb >= 0 && g.nphi[ya] == g.nphi[yb] && (g.nphi[ya] & 1)) {
             FftRow r{};
             r.mode = ROW_PAIR;
             r.ya = ya;
@@ -757,7 +757,7 @@ int fft_plan_build(Plan &p)
     // per-ring tables
     std::vector<int> slot_of_ring(g.nrings, -1);
     for (int i = 0; i < p.nslots; ++i) {
-        slot_of_ring[p.slots[i].yn] = i;
+        if (p.slots[i].yn >= 0) slot_of_ring[p.slots[i].yn] = i;
         if (p.slots[i].ys >= 0) slot_of_ring[p.slots[i].ys] = i;
     }
     std::vector<int> mvalid(g.nrings, -1);

@@ -311,13 +311,13 @@ static void plan_free_device(Plan *p)
     dev_free(p->d_slot_cos); dev_free(p->d_slot_sin);
     dev_free(p->d_slot_chalf); dev_free(p->d_slot_shalf);
     dev_free(p->d_slot_yn); dev_free(p->d_slot_ys);
-    dev_free(p->d_coef); dev_free(p->d_coef_ofs); dev_free(p->d_start);
+    dev_free(p->d_coef); dev_free(p->d_fl); dev_free(p->d_coef_ofs); dev_free(p->d_start);
     dev_free(p->d_tile_mlim); dev_free(p->d_synth_items); dev_free(p->d_anal_ms);
     dev_free(p->d_phase);
     fft_plan_free(p->fft);
     p->d_slot_cos = p->d_slot_sin = p->d_slot_chalf = p->d_slot_shalf = nullptr;
     p->d_slot_yn = p->d_slot_ys = nullptr;
-    p->d_coef = nullptr; p->d_coef_ofs = nullptr; p->d_start = nullptr;
+    p->d_coef = nullptr; p->d_fl = nullptr; p->d_coef_ofs = nullptr; p->d_start = nullptr;
     p->d_tile_mlim = nullptr; p->d_synth_items = nullptr; p->d_anal_ms = nullptr;
     p->d_phase = nullptr;
 }
@@ -335,31 +335,29 @@ static void build_slots(Plan &p)
                      [&](int a, int b) { return g.theta[a] < g.theta[b]; });
     const double tol = 8.0 * M_PI * 2.220446049250313e-16;
     p.slots.clear();
-    int i = 0, j = g.nrings - 1;
-    auto single = [&](int y) {
+    auto make = [&](int yn, int ys, double t) {
         SlotHost s;
-        s.yn = y;
-        s.ys = -1;
-        double t = g.theta[y];
+        s.yn = yn;
+        s.ys = ys;
         s.cth = cos(t);
         s.sth = sin(t);
         s.chalf = cos(0.5 * t);
         s.shalf = sin(0.5 * t);
         p.slots.push_back(s);
     };
+    // a ring beyond the equator is represented by its mirror colatitude
+    auto single = [&](int y) {
+        double t = g.theta[y];
+        if (t <= 0.5 * M_PI) make(y, -1, t);
+        else make(-1, y, M_PI - t);
+    };
+    int i = 0, j = g.nrings - 1;
     while (i <= j) {
         if (i == j) { single(idx[i]); break; }
         double ti = g.theta[idx[i]], tj = g.theta[idx[j]];
         double d = ti + tj - M_PI;
         if (fabs(d) <= tol && ti <= 0.5 * M_PI) {
-            SlotHost s;
-            s.yn = idx[i];
-            s.ys = idx[j];
-            s.cth = cos(ti);
-            s.sth = sin(ti);
-            s.chalf = cos(0.5 * ti);
-            s.shalf = sin(0.5 * ti);
-            p.slots.push_back(s);
+            make(idx[i], idx[j], ti);
             ++i;
             --j;
         } else if (d < 0) {
@@ -404,13 +402,15 @@ static int slot_mlim(const Plan &p, const SlotHost &s)
 // multiply-adds per step, alpha_l = P_l f_l / f_{l+1}, beta_l = alpha_l c_l.
 // All l-only factors are computed once per m and reused for every ring
 // (Sect. 4.1: "re-used for different colatitudes").
-static void build_coef(Plan &p, std::vector<double4> &coef, std::vector<int64_t> &ofs)
+static void build_coef(Plan &p, std::vector<double4> &coef, std::vector<double> &fl,
+                       std::vector<int64_t> &ofs)
 {
     const int s = p.spin;
     ofs.assign(p.mmax + 1, 0);
     int64_t total = 0;
     for (int m = 0; m <= p.mmax; ++m) total += p.lmax + 1 - std::max(m, s);
     coef.assign((size_t)std::max<int64_t>(total, 1), double4{0, 0, 0, 0});
+    fl.assign((size_t)std::max<int64_t>(total, 1), 0.0);
     int64_t base = 0;
     for (int m = 0; m <= p.mmax; ++m) {
         const int l0 = std::max(m, s);
@@ -430,12 +430,17 @@ static void build_coef(Plan &p, std::vector<double4> &coef, std::vector<int64_t>
             long double f_next = (l == l0) ? 1.0L : Q * f_prev;
             long double alpha = P * f_cur / f_next;
             if (l == p.lmax) alpha = 0.0L;
+            const long double beta = alpha * c;
             double4 e;
             e.x = (double)alpha;
-            e.y = (double)(alpha * c);
-            e.z = (double)f_cur;
-            e.w = 0.0;
+            e.y = (double)beta;
+            // t - 2 = (alpha +- beta - 2) - 2 alpha sin^2(t/2): the small part
+            // is formed here in long double, so that near the poles the
+            // recursion sees 1 - cos t at full relative precision
+            e.z = (double)(alpha + beta - 2.0L);
+            e.w = (double)(alpha - beta - 2.0L);
             coef[(size_t)(base + (l - l0))] = e;
+            fl[(size_t)(base + (l - l0))] = (double)f_cur;
             f_prev = f_cur;
             f_cur = f_next;
         }
@@ -561,10 +566,13 @@ static int plan_build(Plan &p)
     if ((rc = dev_upload(p.d_slot_ys, ys.data(), ns * sizeof(int), "upload"))) return rc;
 
     std::vector<double4> coef;
+    std::vector<double> fl;
     std::vector<int64_t> cofs;
-    build_coef(p, coef, cofs);
+    build_coef(p, coef, fl, cofs);
     if ((rc = dev_alloc((void **)&p.d_coef, coef.size() * sizeof(double4), "coefficient table"))) return rc;
     if ((rc = dev_upload(p.d_coef, coef.data(), coef.size() * sizeof(double4), "upload"))) return rc;
+    if ((rc = dev_alloc((void **)&p.d_fl, fl.size() * sizeof(double), "coefficient table"))) return rc;
+    if ((rc = dev_upload(p.d_fl, fl.data(), fl.size() * sizeof(double), "upload"))) return rc;
     if ((rc = dev_alloc((void **)&p.d_coef_ofs, cofs.size() * sizeof(int64_t), "coefficient table"))) return rc;
     if ((rc = dev_upload(p.d_coef_ofs, cofs.data(), cofs.size() * sizeof(int64_t), "upload"))) return rc;
 
@@ -576,11 +584,25 @@ static int plan_build(Plan &p)
     if ((rc = dev_alloc((void **)&p.d_tile_mlim, p.ntiles * sizeof(int), "tile table"))) return rc;
     if ((rc = dev_upload(p.d_tile_mlim, p.tile_mlim.data(), p.ntiles * sizeof(int), "upload"))) return rc;
 
-    // synthesis work items: (m, tile) with an active slot, larger l-ranges first
+    // synthesis work items: m and up to LEG_NW active tiles, larger l-ranges first
     p.synth_items.clear();
-    for (int m = 0; m <= p.mmax; ++m)
-        for (int t = 0; t < p.ntiles; ++t)
-            if (p.tile_mlim[t] >= m) p.synth_items.push_back(LegItem{m, t});
+    for (int m = 0; m <= p.mmax; ++m) {
+        LegItem it;
+        it.m = m;
+        int n = 0;
+        for (int t = 0; t < p.ntiles; ++t) {
+            if (p.tile_mlim[t] < m) continue;
+            it.tile[n++] = t;
+            if (n == LEG_NW) {
+                p.synth_items.push_back(it);
+                n = 0;
+            }
+        }
+        if (n) {
+            for (int k = n; k < LEG_NW; ++k) it.tile[k] = -1;
+            p.synth_items.push_back(it);
+        }
+    }
     p.n_items = (int64_t)p.synth_items.size();
     if (!p.synth_items.empty()) {
         if ((rc = dev_alloc((void **)&p.d_synth_items, p.synth_items.size() * sizeof(LegItem), "item list"))) return rc;
@@ -610,7 +632,7 @@ LegView make_leg_view(const Plan &p)
     v.slot_cos = p.d_slot_cos; v.slot_sin = p.d_slot_sin;
     v.slot_chalf = p.d_slot_chalf; v.slot_shalf = p.d_slot_shalf;
     v.slot_yn = p.d_slot_yn; v.slot_ys = p.d_slot_ys;
-    v.coef = p.d_coef; v.coef_ofs = p.d_coef_ofs; v.start = p.d_start;
+    v.coef = p.d_coef; v.fl = p.d_fl; v.coef_ofs = p.d_coef_ofs; v.start = p.d_start;
     v.tile_mlim = p.d_tile_mlim;
     v.nalm = p.nalm;
     return v;
@@ -700,7 +722,8 @@ void sht_plan_destroy(sht_plan *h)
 static int check_exec_args(Plan *p, int direction, const double *in, double *out, bool stage_fft,
                            bool stage_leg)
 {
-    if (direction != SHT_ALM2MAP && direction != SHT_MAP2ALM && direction != SHT_ALM2MAP_ADJOINT) {
+    if (direction != SHT_ALM2MAP && direction != SHT_MAP2ALM && direction != SHT_ALM2MAP_ADJOINT &&
+        direction != SHT_ALM2MAP_GRAD) {
         set_error("unknown direction %d", direction);
         return SHT_EINVAL;
     }
@@ -749,7 +772,7 @@ int sht_execute(sht_plan *h, int direction, const double *in, double *out, void 
         if ((rc = launch_ring_synth(*p, p->d_phase, out, s))) return rc;
     } else {
         if ((rc = launch_ring_anal(*p, in, p->d_phase, direction == SHT_MAP2ALM, s))) return rc;
-        if ((rc = launch_legendre_anal(*p, p->d_phase, out, s))) return rc;
+        if ((rc = launch_legendre_anal(*p, p->d_phase, out, direction == SHT_ALM2MAP_GRAD, s))) return rc;
     }
     return finish_launch("sht_execute");
 }
@@ -762,7 +785,7 @@ int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     if (direction == SHT_ALM2MAP) rc = launch_legendre_synth(*p, in, out, s);
-    else rc = launch_legendre_anal(*p, in, out, s);
+    else rc = launch_legendre_anal(*p, in, out, direction == SHT_ALM2MAP_GRAD, s);
     if (rc) return rc;
     return finish_launch("sht_legendre");
 }

@@ -29,16 +29,20 @@ struct Geom {
 };
 
 // One recurrence chain slot: a ring and (optionally) its mirror ring.
+// The recursion runs at the representative colatitude t <= pi/2 of the slot;
+// the ring at pi - t (if any) follows from the parity relation.
 struct SlotHost {
-    int yn = -1, ys = -1;       // north ring (theta <= pi/2) and its mirror (-1: none)
-    double cth = 0, sth = 0;    // cos/sin theta of the north ring
-    double chalf = 0, shalf = 0;  // cos/sin theta/2
+    int yn = -1, ys = -1;       // ring at t and ring at pi - t (-1: none)
+    double cth = 0, sth = 0;    // cos t >= 0, sin t
+    double chalf = 0, shalf = 0;  // cos t/2, sin t/2
 };
 
-// Legendre work item (device layout): one (m, tile of slots).
+constexpr int LEG_NW = 4;       // wavefronts per Legendre work group
+
+// Synthesis work item: one m and up to LEG_NW slot tiles (-1: none).
 struct LegItem {
     int m;
-    int tile;
+    int tile[LEG_NW];
 };
 
 // Per-(m, chain) start value: lambda_{l0} = sign * K * cos(t/2)^p * sin(t/2)^q.
@@ -58,8 +62,9 @@ struct LegView {
     double polar_T;         // Eq. 8 (<0: no polar skip)
     const double *slot_cos, *slot_sin, *slot_chalf, *slot_shalf;
     const int *slot_yn, *slot_ys;
-    const double4 *coef;        // (alpha, beta, f, 0) per (m, l)
-    const int64_t *coef_ofs;    // coef + coef_ofs[m] + l  for l >= l0(m)
+    const double4 *coef;        // (alpha, beta, delta+, delta-) per (m, l)
+    const double *fl;           // f_l per (m, l): lambda = f mu
+    const int64_t *coef_ofs;    // coef + coef_ofs[m] + l  for l >= l0(m) (same for fl)
     const StartCoef *start;     // [m][chain] chain 0: +s (or 0), chain 1: -s
     const int *tile_mlim;       // per tile: largest m with an active slot (-1: none)
     int64_t nalm;
@@ -101,6 +106,7 @@ struct Plan {
            *d_slot_shalf = nullptr;
     int *d_slot_yn = nullptr, *d_slot_ys = nullptr;
     double4 *d_coef = nullptr;
+    double *d_fl = nullptr;
     int64_t *d_coef_ofs = nullptr;
     StartCoef *d_start = nullptr;
     int *d_tile_mlim = nullptr;
@@ -124,7 +130,7 @@ LegView make_leg_view(const Plan &p);
 
 // Legendre step launchers (legendre.hip)
 int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipStream_t s);
-int launch_legendre_anal(const Plan &p, const double *phase, double *alm, hipStream_t s);
+int launch_legendre_anal(const Plan &p, const double *phase, double *alm, bool grad, hipStream_t s);
 
 // ring FFT (ringfft.hip)
 int fft_plan_build(Plan &p);

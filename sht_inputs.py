@@ -166,25 +166,26 @@ def random_alm(lmax: int, mmax: int, ntrans: int = 1, spin: int = 0,
     ncomp = 2 if spin else 1
     ls, ms = lm_arrays(lmax, mmax)
     n = ls.shape[0]
-    out = np.zeros((ntrans, ncomp, n, 2))
+    if spectrum == "unit":
+        sd_re = np.ones(n)
+        sd_im = np.where(ms == 0, 0.0, 1.0)
+    elif spectrum == "powerlaw":
+        cl = 1.0 / (ls + 1.0) ** 2
+        sd_re = np.where(ms == 0, np.sqrt(cl), np.sqrt(cl / 2.0))
+        sd_im = np.where(ms == 0, 0.0, np.sqrt(cl / 2.0))
+    else:
+        raise ValueError(spectrum)
+    if spin:
+        sd_re = np.where(ls < spin, 0.0, sd_re)
+        sd_im = np.where(ls < spin, 0.0, sd_im)
+    out = np.empty((ntrans, ncomp, n, 2))
     for t in range(ntrans):
         for c in range(ncomp):
             rng = np.random.default_rng([SEED_ROOT, tag, t, c])
-            re = rng.standard_normal(n)
-            im = rng.standard_normal(n)
-            if spectrum == "unit":
-                sd_re = np.ones(n)
-                sd_im = np.ones(n)
-            elif spectrum == "powerlaw":
-                cl = 1.0 / (ls + 1.0) ** 2
-                sd_re = np.where(ms == 0, np.sqrt(cl), np.sqrt(cl / 2.0))
-                sd_im = np.sqrt(cl / 2.0)
-            else:
-                raise ValueError(spectrum)
-            out[t, c, :, 0] = re * sd_re
-            out[t, c, :, 1] = np.where(ms == 0, 0.0, im * sd_im)
-            if spin:
-                out[t, c, ls < spin, :] = 0.0
+            out[t, c, :, 0] = rng.standard_normal(n)
+            out[t, c, :, 1] = rng.standard_normal(n)
+            out[t, c, :, 0] *= sd_re
+            out[t, c, :, 1] *= sd_im
     return out
 
 
