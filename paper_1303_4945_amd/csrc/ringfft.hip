@@ -13,8 +13,10 @@
 // mixed-radix transform (decimation in frequency: natural -> digit-reversed
 // order; decimation in time: digit-reversed -> natural), the spectrum being
 // read or written at digit-reversed positions so that no permutation pass is
-// needed.  Other lengths use Bluestein's chirp transform with a power-of-two
-// inner length M (>= 2L-1); when M complex doubles exceed the LDS, the inner
+// needed.  A prime L whose L-1 factors that way uses Rader's reordering into a
+// cyclic convolution of length L-1 (two in-LDS transforms of length L-1).
+// Other lengths use Bluestein's chirp transform with a power-of-two inner
+// length M (>= 2L-1); when M complex doubles exceed the LDS, the inner
 // transform is split by one radix-2 step into two halves processed one after
 // the other, the first half's result being kept in registers.
 #include <hip/hip_runtime.h>
@@ -22,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <tuple>
 #include <vector>
 
 #include "sht_internal.h"
@@ -30,7 +33,10 @@ namespace sht {
 
 constexpr int FFT_MAXRAD = 16;
 
-enum { FFT_DIRECT = 0, FFT_BLUE = 1, FFT_BLUE_SPLIT = 2 };
+enum { FFT_DIRECT = 0, FFT_BLUE = 1, FFT_BLUE_SPLIT = 2, FFT_RADER = 3 };
+// kernel variants: everything in LDS / split Bluestein / Rader
+enum { KMODE_LDS = 0, KMODE_SPLIT = 1, KMODE_RADER = 2 };
+constexpr int FFT_NREG = 8;   // register slots per thread in split and Rader mode
 enum { ROW_PAIR = 0, ROW_HALF = 1 };
 
 struct FftInner {       // an in-LDS complex FFT of length n
@@ -44,12 +50,15 @@ struct FftInner {       // an in-LDS complex FFT of length n
 struct FftLen {         // complex transform of length L
     int L;
     int kind;
-    int M;              // Bluestein inner length (full M, also in split mode)
-    int inner;          // index of the FftInner used (length L, M or M/2)
-    int64_t chirp;      // L entries e^{+i pi n^2 / L}
+    int M;              // Bluestein inner length (full M, also in split mode); Rader: L-1
+    int inner;          // index of the FftInner used (length L, M, M/2 or L-1)
+    int64_t chirp;      // Bluestein: L entries e^{+i pi n^2 / L};
+                        // Rader: L-1 entries b_q = e^{+2 pi i g^{-q} / L}
     int64_t bhat_p;     // kernel spectrum for sign +  (M entries; split: even half then odd half)
     int64_t bhat_m;     // kernel spectrum for sign -
     int64_t wm;         // split: e^{-2 pi i n / M}, n < M/2
+    int64_t gpow;       // Rader: itab offset of g^p mod L, p < L-1
+    int64_t qpos;       // Rader: itab offset of q(k) with g^{-q} = k mod L, 0 < k < L
     int lds_complex;    // LDS buffer size in complex elements
 };
 
@@ -78,6 +87,11 @@ struct FftView {
 };
 
 // ------------------------------------------------------------------ device
+
+// LDS index with one complex of padding every 8 elements: the strided
+// butterfly accesses of radix 2, 4 and 8 then fall into distinct bank groups.
+__device__ __forceinline__ int PADI(int i) { return i + (i >> 3); }
+constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -152,18 +166,19 @@ __device__ __forceinline__ void small_dft(double2 *v, bool fwd, const double2 *t
 
 // one pass over the block of length Lb split by radix R (stride Ln = Lb / R)
 template <int R, bool DIT>
-__device__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
+__device__ __forceinline__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
 {
     const int Ln = Lb / R;
     const int nb = n / R;
     const int tstep = n / Lb;
+#pragma unroll 1
     for (int q = threadIdx.x; q < nb; q += blockDim.x) {
         const int b = q / Ln;
         const int n1 = q - b * Ln;
         const int base = b * Lb + n1;
         double2 v[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = buf[base + j * Ln];
+        for (int j = 0; j < R; ++j) v[j] = buf[PADI(base + j * Ln)];
         if constexpr (DIT) {
 #pragma unroll
             for (int j = 1; j < R; ++j) {
@@ -180,55 +195,164 @@ __device__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, const double2 *t
             }
         }
 #pragma unroll
-        for (int j = 0; j < R; ++j) buf[base + j * Ln] = v[j];
+        for (int j = 0; j < R; ++j) buf[PADI(base + j * Ln)] = v[j];
     }
     __syncthreads();
 }
 
-template <bool DIT>
-__device__ void fft_pass_any(double2 *buf, int n, int Lb, int r, bool fwd, const double2 *tw)
+// cos and sin of 2 pi m / R for m = 1 .. (R-1)/2 (index 0 unused), rounded
+// from extended-precision values
+template <int R> struct OddRoots;
+template <> struct OddRoots<3> {
+    static constexpr double c[2] = {1.0, -0.5};
+    static constexpr double s[2] = {0.0, 0.8660254037844386};
+};
+template <> struct OddRoots<5> {
+    static constexpr double c[3] = {1.0, 0.30901699437494745, -0.8090169943749475};
+    static constexpr double s[3] = {0.0, 0.9510565162951535, 0.5877852522924731};
+};
+template <> struct OddRoots<7> {
+    static constexpr double c[4] = {1.0, 0.6234898018587335, -0.2225209339563144,
+                                    -0.9009688679024191};
+    static constexpr double s[4] = {0.0, 0.7818314824680298, 0.9749279121818236,
+                                    0.4338837391175581};
+};
+template <> struct OddRoots<11> {
+    static constexpr double c[6] = {1.0, 0.8412535328311812, 0.41541501300188644,
+                                    -0.14231483827328514, -0.6548607339452851,
+                                    -0.9594929736144974};
+    static constexpr double s[6] = {0.0, 0.5406408174555976, 0.9096319953545183,
+                                    0.9898214418809327, 0.7557495743542583,
+                                    0.28173255684142967};
+};
+template <> struct OddRoots<13> {
+    static constexpr double c[7] = {1.0, 0.8854560256532099, 0.5680647467311558,
+                                    0.12053668025532305, -0.3546048870425356,
+                                    -0.7485107481711011, -0.970941817426052};
+    static constexpr double s[7] = {0.0, 0.46472317204376856, 0.8229838658936564,
+                                    0.992708874098054, 0.9350162426854148,
+                                    0.6631226582407952, 0.23931566428755777};
+};
+
+// One pass with an odd radix R, in the symmetric form: with s_j = v_j + v_{R-j}
+// and d_j = v_j - v_{R-j}, out_k = A_k - i B_k and out_{R-k} = A_k + i B_k where
+// A_k = v_0 + sum_j s_j cos(2 pi jk/R) and B_k = sum_j d_j sin(2 pi jk/R) (sine
+// sign flipped for the inverse).  Outputs go to LDS as soon as they are formed,
+// so no second register array is live.
+template <int R, bool DIT>
+__device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
+{
+    constexpr int H = (R - 1) / 2;
+    const int Ln = Lb / R;
+    const int nb = n / R;
+    const int tstep = n / Lb;
+    const double ssign = fwd ? 1.0 : -1.0;   // w^m = cos - i ssign sin
+#pragma unroll 1
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        const int b = q / Ln;
+        const int n1 = q - b * Ln;
+        const int base = b * Lb + n1;
+        double2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = buf[PADI(base + j * Ln)];
+        if constexpr (DIT) {
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                double2 t = tw[tstep * n1 * j];
+                v[j] = cmul(v[j], fwd ? t : cconj(t));
+            }
+        }
+        const double2 v0 = v[0];
+        double2 sum0 = v0;
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const double2 sj = cadd(v[j], v[R - j]);
+            const double2 dj = csub(v[j], v[R - j]);
+            v[j] = sj;
+            v[R - j] = dj;
+            sum0 = cadd(sum0, sj);
+        }
+        buf[PADI(base)] = sum0;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            double2 A = v0, B = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 1; j <= H; ++j) {
+                const int m = (j * k) % R;
+                const double c = (m <= H) ? OddRoots<R>::c[m] : OddRoots<R>::c[R - m];
+                const double sn = ssign * ((m <= H) ? OddRoots<R>::s[m] : -OddRoots<R>::s[R - m]);
+                A.x += v[j].x * c;
+                A.y += v[j].y * c;
+                B.x += v[R - j].x * sn;
+                B.y += v[R - j].y * sn;
+            }
+            double2 ok = make_double2(A.x + B.y, A.y - B.x);
+            double2 okr = make_double2(A.x - B.y, A.y + B.x);
+            if constexpr (!DIT) {
+                const double2 t1 = tw[tstep * n1 * k], t2 = tw[tstep * n1 * (R - k)];
+                ok = cmul(ok, fwd ? t1 : cconj(t1));
+                okr = cmul(okr, fwd ? t2 : cconj(t2));
+            }
+            buf[PADI(base + k * Ln)] = ok;
+            buf[PADI(base + (R - k) * Ln)] = okr;
+        }
+    }
+    __syncthreads();
+}
+
+// POW2: only radices 2, 4, 8 occur (keeps the odd-radix code, and its
+// registers, out of the power-of-two kernels)
+template <bool DIT, bool POW2>
+__device__ __forceinline__ void fft_pass_any(double2 *buf, int n, int Lb, int r, bool fwd, const double2 *tw)
 {
     switch (r) {
     case 2: fft_pass<2, DIT>(buf, n, Lb, fwd, tw); break;
-    case 3: fft_pass<3, DIT>(buf, n, Lb, fwd, tw); break;
     case 4: fft_pass<4, DIT>(buf, n, Lb, fwd, tw); break;
-    case 5: fft_pass<5, DIT>(buf, n, Lb, fwd, tw); break;
-    case 7: fft_pass<7, DIT>(buf, n, Lb, fwd, tw); break;
     case 8: fft_pass<8, DIT>(buf, n, Lb, fwd, tw); break;
-    case 11: fft_pass<11, DIT>(buf, n, Lb, fwd, tw); break;
-    case 13: fft_pass<13, DIT>(buf, n, Lb, fwd, tw); break;
-    default: break;
+    default:
+        if constexpr (!POW2) {
+            switch (r) {
+            case 3: fft_pass_odd<3, DIT>(buf, n, Lb, fwd, tw); break;
+            case 5: fft_pass_odd<5, DIT>(buf, n, Lb, fwd, tw); break;
+            case 7: fft_pass_odd<7, DIT>(buf, n, Lb, fwd, tw); break;
+            case 11: fft_pass_odd<11, DIT>(buf, n, Lb, fwd, tw); break;
+            case 13: fft_pass_odd<13, DIT>(buf, n, Lb, fwd, tw); break;
+            default: break;
+            }
+        }
+        break;
     }
 }
 
 // natural order in, digit-reversed out
-__device__ void fft_dif(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
+template <bool POW2>
+__device__ __forceinline__ void fft_dif(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
 {
     const double2 *tw = ctab + in.tw;
     int Lb = in.n;
     for (int i = 0; i < in.nrad; ++i) {
-        fft_pass_any<false>(buf, in.n, Lb, in.rad[i], fwd, tw);
+        fft_pass_any<false, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
         Lb /= in.rad[i];
     }
 }
 
 // digit-reversed in, natural order out
-__device__ void fft_dit(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
+template <bool POW2>
+__device__ __forceinline__ void fft_dit(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
 {
     const double2 *tw = ctab + in.tw;
     int Lb = 1;
     for (int i = in.nrad - 1; i >= 0; --i) {
         Lb *= in.rad[i];
-        fft_pass_any<true>(buf, in.n, Lb, in.rad[i], fwd, tw);
+        fft_pass_any<true, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
     }
 }
 
 // Complex DFT of length L with sign fwd (e^{-}) or inverse (e^{+}), natural
-// order in and out, for the Bluestein kinds.  buf holds the input x_n, n < L;
-// on return buf holds X_k, k < L.  Uses LDS buf (size lds_complex) and, in
-// split mode, the register arrays of the calling thread (NREG per thread).
-template <int NREG>
-__device__ void bluestein(double2 *buf, const FftView &fv, const FftLen &d, bool fwd)
+// order in and out, by Bluestein's chirp convolution of length M (a power of
+// two).  buf holds the input x_n, n < L; on return buf holds X_k, k < L.
+template <bool POW2>
+__device__ __forceinline__ void bluestein(double2 *buf, const FftView &fv, const FftLen &d, bool fwd)
 {
     const FftInner &in = fv.inner[d.inner];
     const double2 *chirp = fv.ctab + d.chirp;
@@ -236,76 +360,70 @@ __device__ void bluestein(double2 *buf, const FftView &fv, const FftLen &d, bool
     const int L = d.L;
     // chirp for sign s: w_n = e^{s i pi n^2/L}; table holds s = +
     auto wch = [&](int n) { double2 c = chirp[n]; return fwd ? cconj(c) : c; };
-    if (d.kind == FFT_BLUE) {
-        const int M = d.M;
-        for (int n = threadIdx.x; n < M; n += blockDim.x) {
-            double2 a = make_double2(0.0, 0.0);
-            if (n < L) a = cmul(buf[n], wch(n));
-            buf[n] = a;
-        }
-        __syncthreads();
-        fft_dif(buf, in, true, fv.ctab);
-        for (int p = threadIdx.x; p < M; p += blockDim.x) buf[p] = cmul(buf[p], bh[p]);
-        __syncthreads();
-        fft_dit(buf, in, false, fv.ctab);
-        for (int k = threadIdx.x; k < L; k += blockDim.x) buf[k] = cmul(buf[k], wch(k));
-        __syncthreads();
-    } else {
-        const int Mh = d.M / 2;
-        const double2 *wm = fv.ctab + d.wm;
-        double2 xr[NREG], er[NREG];
-        // keep the chirped input in registers
-#pragma unroll
-        for (int j = 0; j < NREG; ++j) {
-            const int n = threadIdx.x + j * blockDim.x;
-            xr[j] = (n < L) ? cmul(buf[n], wch(n)) : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        // even half: FFT_{M/2}(a), times kernel, inverse
-#pragma unroll
-        for (int j = 0; j < NREG; ++j) {
-            const int n = threadIdx.x + j * blockDim.x;
-            if (n < Mh) buf[n] = xr[j];
-        }
-        __syncthreads();
-        fft_dif(buf, in, true, fv.ctab);
-        for (int p = threadIdx.x; p < Mh; p += blockDim.x) buf[p] = cmul(buf[p], bh[p]);
-        __syncthreads();
-        fft_dit(buf, in, false, fv.ctab);
-#pragma unroll
-        for (int j = 0; j < NREG; ++j) {
-            const int n = threadIdx.x + j * blockDim.x;
-            er[j] = (n < Mh) ? buf[n] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        // odd half: FFT_{M/2}(a_n w_M^n)
-#pragma unroll
-        for (int j = 0; j < NREG; ++j) {
-            const int n = threadIdx.x + j * blockDim.x;
-            if (n < Mh) buf[n] = cmul(xr[j], wm[n]);
-        }
-        __syncthreads();
-        fft_dif(buf, in, true, fv.ctab);
-        for (int p = threadIdx.x; p < Mh; p += blockDim.x) buf[p] = cmul(buf[p], bh[Mh + p]);
-        __syncthreads();
-        fft_dit(buf, in, false, fv.ctab);
-        // c_n = E_n + w_M^{-n} O_n ; X_k = w_k c_k
-#pragma unroll
-        for (int j = 0; j < NREG; ++j) {
-            const int n = threadIdx.x + j * blockDim.x;
-            if (n < L) {
-                double2 c = cadd(er[j], cmul(buf[n], cconj(wm[n])));
-                xr[j] = cmul(c, wch(n));
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < NREG; ++j) {
-            const int n = threadIdx.x + j * blockDim.x;
-            if (n < L) buf[n] = xr[j];
-        }
-        __syncthreads();
+    const int M = d.M;
+    for (int n = threadIdx.x; n < M; n += blockDim.x) {
+        double2 a = make_double2(0.0, 0.0);
+        if (n < L) a = cmul(buf[PADI(n)], wch(n));
+        buf[PADI(n)] = a;
     }
+    __syncthreads();
+    fft_dif<POW2>(buf, in, true, fv.ctab);
+    for (int p = threadIdx.x; p < M; p += blockDim.x) buf[PADI(p)] = cmul(buf[PADI(p)], bh[p]);
+    __syncthreads();
+    fft_dit<POW2>(buf, in, false, fv.ctab);
+    for (int k = threadIdx.x; k < L; k += blockDim.x) buf[PADI(k)] = cmul(buf[PADI(k)], wch(k));
+    __syncthreads();
+}
+
+// Bluestein with the length-M convolution done as two length-M/2 halves (even
+// and odd output frequencies of the first radix-2 step), for lengths whose M
+// does not fit LDS.  The input is not kept: load(n) produces x_n (n < L) again
+// for the second half.  Requires NREG * blockDim.x >= M/2.  On return buf holds
+// X_k, k < L, in natural order.
+template <int NREG, bool POW2, typename Load>
+__device__ __forceinline__ void bluestein_split(double2 *buf, const FftView &fv, const FftLen &d, bool fwd,
+                                Load load)
+{
+    const FftInner &in = fv.inner[d.inner];
+    const double2 *chirp = fv.ctab + d.chirp;
+    const double2 *bh = fv.ctab + (fwd ? d.bhat_m : d.bhat_p);
+    const int L = d.L;
+    auto wch = [&](int n) { double2 c = chirp[n]; return fwd ? cconj(c) : c; };
+    const int Mh = d.M / 2;
+    const double2 *wm = fv.ctab + d.wm;
+    double2 er[NREG];
+    // even frequencies: FFT_{M/2}(a), a_n = x_n w_n, times kernel, inverse
+    for (int n = threadIdx.x; n < Mh; n += blockDim.x)
+        buf[PADI(n)] = (n < L) ? cmul(load(n), wch(n)) : make_double2(0.0, 0.0);
+    __syncthreads();
+    fft_dif<POW2>(buf, in, true, fv.ctab);
+    for (int p = threadIdx.x; p < Mh; p += blockDim.x) buf[PADI(p)] = cmul(buf[PADI(p)], bh[p]);
+    __syncthreads();
+    fft_dit<POW2>(buf, in, false, fv.ctab);
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+        const int n = threadIdx.x + j * blockDim.x;
+        er[j] = (n < Mh) ? buf[PADI(n)] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // odd frequencies: FFT_{M/2}(a_n w_M^n)
+    for (int n = threadIdx.x; n < Mh; n += blockDim.x)
+        buf[PADI(n)] = (n < L) ? cmul(cmul(load(n), wch(n)), wm[n]) : make_double2(0.0, 0.0);
+    __syncthreads();
+    fft_dif<POW2>(buf, in, true, fv.ctab);
+    for (int p = threadIdx.x; p < Mh; p += blockDim.x) buf[PADI(p)] = cmul(buf[PADI(p)], bh[Mh + p]);
+    __syncthreads();
+    fft_dit<POW2>(buf, in, false, fv.ctab);
+    // c_n = E_n + w_M^{-n} O_n ; X_n = w_n c_n (each thread rewrites its own entries)
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+        const int n = threadIdx.x + j * blockDim.x;
+        if (n < L) {
+            const double2 c = cadd(er[j], cmul(buf[PADI(n)], cconj(wm[n])));
+            buf[PADI(n)] = cmul(c, wch(n));
+        }
+    }
+    __syncthreads();
 }
 
 // e^{i m phi0} of ring y for 0 <= m (fine/coarse split by 64)
@@ -317,7 +435,7 @@ __device__ __forceinline__ double2 ring_rot(const FftView &fv, int y, int m)
 
 // Folded Hermitian spectrum bin k of ring y for component row `row`:
 // b_k = sum over m = k mod N, |m| <= mv, of F_m e^{i m phi0} (conjugated for m < 0).
-__device__ double2 fold_bin(const FftView &fv, const double2 *Frow, int y, int N, int mv, int k)
+__device__ __forceinline__ double2 fold_bin(const FftView &fv, const double2 *Frow, int y, int N, int mv, int k)
 {
     double2 s = make_double2(0.0, 0.0);
     for (int m = k; m <= mv; m += N) s = cadd(s, cmul(Frow[m], ring_rot(fv, y, m)));
@@ -328,8 +446,110 @@ __device__ double2 fold_bin(const FftView &fv, const double2 *Frow, int y, int N
     return s;
 }
 
-template <int NREG>
-__global__ __launch_bounds__(512) void k_ring_synth(FftView fv, const int *__restrict__ rowlist,
+// Rader's algorithm for a prime length L with smooth L-1: with a generator g
+// of the multiplicative group mod L, a_p = x_{g^p} and b_q = w^{g^{-q}}
+// (w = e^{-+2 pi i / L}), X_{g^{-q}} = x_0 + (a (*) b)_q, a cyclic convolution of
+// length L-1 done with two in-LDS transforms.  buf holds x_n in natural order
+// on entry; on return buf[q] holds (a (*) b)_q, and x0 = x_0, X0 = X_0 = sum x_n.
+// Requires FFT_NREG * blockDim.x >= L - 1.
+struct RaderEnds {
+    double2 x0, X0;
+};
+
+template <bool POW2>
+__device__ __forceinline__ RaderEnds rader(double2 *buf, const FftView &fv, const FftLen &d, bool fwd)
+{
+    const FftInner &in = fv.inner[d.inner];
+    const int Lm = d.L - 1;
+    const int *gp = fv.itab + d.gpow;
+    const double2 *bh = fv.ctab + (fwd ? d.bhat_m : d.bhat_p);
+    // staged as separate real arrays: element-wise copies of double2 between
+    // LDS and a private array keep the array out of registers
+    double are[FFT_NREG], aim[FFT_NREG];
+    const double2 x0 = buf[PADI(0)];
+#pragma unroll
+    for (int j = 0; j < FFT_NREG; ++j) {
+        const int p = threadIdx.x + j * blockDim.x;
+        const double2 t = buf[PADI(p < Lm ? gp[p] : 0)];
+        are[j] = t.x;
+        aim[j] = t.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FFT_NREG; ++j) {
+        const int p = threadIdx.x + j * blockDim.x;
+        if (p < Lm) buf[PADI(p)] = make_double2(are[j], aim[j]);
+    }
+    __syncthreads();
+    fft_dif<POW2>(buf, in, true, fv.ctab);
+    const double2 A0 = buf[PADI(0)];        // DC of the reordered input: sum_{n>0} x_n
+    __syncthreads();
+    for (int p = threadIdx.x; p < Lm; p += blockDim.x) buf[PADI(p)] = cmul(buf[PADI(p)], bh[p]);
+    __syncthreads();
+    fft_dit<POW2>(buf, in, false, fv.ctab);
+    return RaderEnds{x0, cadd(x0, A0)};
+}
+
+// Spectrum bin k (k < L) of a length-L transform finished in LDS by the mode.
+template <int MODE>
+struct SpecRead {
+    const double2 *buf;
+    const int *pos;      // LDS mode, direct kind: digit-reversed position; else null
+    const int *qpos;     // Rader
+    double2 x0, X0;
+    __device__ __forceinline__ double2 operator()(int k) const
+    {
+        if constexpr (MODE == KMODE_RADER) {
+            if (k == 0) return X0;
+            return cadd(x0, buf[PADI(qpos[k])]);
+        } else {
+            return buf[PADI(pos ? pos[k] : k)];
+        }
+    }
+};
+
+// Runs the length-L transform of the row in LDS.  load(n), n < L, gives the
+// input.  Returns the reader of the result in natural frequency order.
+template <int MODE, bool POW2, typename Load>
+__device__ __forceinline__ SpecRead<MODE> ring_transform(double2 *buf, const FftView &fv,
+                                                         const FftLen &d, bool fwd, Load load)
+{
+    const FftInner &in = fv.inner[d.inner];
+    const int L = d.L;
+    SpecRead<MODE> r{buf, nullptr, nullptr, make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    if constexpr (MODE == KMODE_SPLIT) {
+        bluestein_split<FFT_NREG, POW2>(buf, fv, d, fwd, load);
+    } else if constexpr (MODE == KMODE_RADER) {
+        for (int n = threadIdx.x; n < L; n += blockDim.x) buf[PADI(n)] = load(n);
+        __syncthreads();
+        const RaderEnds e = rader<POW2>(buf, fv, d, fwd);
+        r.x0 = e.x0;
+        r.X0 = e.X0;
+        r.qpos = fv.itab + d.qpos;
+    } else {
+        const bool direct = d.kind == FFT_DIRECT;
+        if (direct && !fwd) {
+            // inverse: spectrum in at digit-reversed positions, signal out natural
+            const int *pos = fv.itab + in.pos;
+            for (int n = threadIdx.x; n < L; n += blockDim.x) buf[PADI(pos[n])] = load(n);
+            __syncthreads();
+            fft_dit<POW2>(buf, in, false, fv.ctab);
+        } else {
+            for (int n = threadIdx.x; n < L; n += blockDim.x) buf[PADI(n)] = load(n);
+            __syncthreads();
+            if (direct) {
+                fft_dif<POW2>(buf, in, true, fv.ctab);
+                r.pos = fv.itab + in.pos;
+            } else {
+                bluestein<POW2>(buf, fv, d, fwd);
+            }
+        }
+    }
+    return r;
+}
+
+template <int MODE, bool POW2>
+__global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__restrict__ rowlist,
                                                     const double *__restrict__ phase,
                                                     double *__restrict__ map)
 {
@@ -337,15 +557,11 @@ __global__ __launch_bounds__(512) void k_ring_synth(FftView fv, const int *__res
     const FftRow row = fv.rows[rowlist[blockIdx.x]];
     const int tc = blockIdx.y;   // transform * ncomp + component
     const FftLen d = fv.lens[row.len];
-    const FftInner &in = fv.inner[d.inner];
     const int N = row.nphi;
     const int64_t rowF = (int64_t)tc * fv.nrings;
     const double2 *Fa = reinterpret_cast<const double2 *>(phase) + (rowF + row.ya) * (fv.mmax + 1);
     const int mva = min(fv.mvalid[row.ya], fv.mmax);
     double *mp = map + (int64_t)tc * fv.npix;
-    const int L = d.L;
-    const bool direct = d.kind == FFT_DIRECT;
-    const int *pos = fv.itab + in.pos;
 
     if (row.mode == ROW_PAIR) {
         const double2 *Fb = nullptr;
@@ -354,18 +570,15 @@ __global__ __launch_bounds__(512) void k_ring_synth(FftView fv, const int *__res
             Fb = reinterpret_cast<const double2 *>(phase) + (rowF + row.yb) * (fv.mmax + 1);
             mvb = min(fv.mvalid[row.yb], fv.mmax);
         }
-        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        auto zin = [&](int k) {
             double2 A = fold_bin(fv, Fa, row.ya, N, mva, k);
             double2 B = make_double2(0.0, 0.0);
             if (Fb) B = fold_bin(fv, Fb, row.yb, N, mvb, k);
-            double2 Z = make_double2(A.x - B.y, A.y + B.x);   // A + iB
-            buf[direct ? pos[k] : k] = Z;
-        }
-        __syncthreads();
-        if (direct) fft_dit(buf, in, false, fv.ctab);
-        else bluestein<NREG>(buf, fv, d, false);
+            return make_double2(A.x - B.y, A.y + B.x);   // A + iB
+        };
+        const SpecRead<MODE> out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
         for (int x = threadIdx.x; x < N; x += blockDim.x) {
-            const double2 z = buf[x];
+            const double2 z = out(x);
             mp[fv.ofs[row.ya] + (int64_t)x * fv.stride] = z.x;
             if (row.yb >= 0) mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] = z.y;
         }
@@ -373,28 +586,24 @@ __global__ __launch_bounds__(512) void k_ring_synth(FftView fv, const int *__res
         // even N = 2h: Z_k = X_k (1 + i w^k) + conj(X_{h-k}) (1 - i w^k), w = e^{2 pi i/N}
         const int h = N / 2;
         const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}
-        for (int k = threadIdx.x; k < h; k += blockDim.x) {
+        auto zin = [&](int k) {
             double2 X = fold_bin(fv, Fa, row.ya, N, mva, k);
             double2 Y = cconj(fold_bin(fv, Fa, row.ya, N, mva, h - k));
             double2 w = cconj(htw[k]);
             double2 iw = make_double2(-w.y, w.x);
-            double2 Z = cadd(cadd(X, cmul(X, iw)), csub(Y, cmul(Y, iw)));
-            buf[direct ? pos[k] : k] = Z;
-        }
-        __syncthreads();
-        if (direct) fft_dit(buf, in, false, fv.ctab);
-        else bluestein<NREG>(buf, fv, d, false);
+            return cadd(cadd(X, cmul(X, iw)), csub(Y, cmul(Y, iw)));
+        };
+        const SpecRead<MODE> out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
         for (int n = threadIdx.x; n < h; n += blockDim.x) {
-            const double2 z = buf[n];
+            const double2 z = out(n);
             mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride] = z.x;
             mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride] = z.y;
         }
     }
-    (void)L;
 }
 
-template <int NREG>
-__global__ __launch_bounds__(512) void k_ring_anal(FftView fv, const int *__restrict__ rowlist,
+template <int MODE, bool POW2>
+__global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__restrict__ rowlist,
                                                    const double *__restrict__ map,
                                                    double *__restrict__ phase, int use_weights)
 {
@@ -402,23 +611,17 @@ __global__ __launch_bounds__(512) void k_ring_anal(FftView fv, const int *__rest
     const FftRow row = fv.rows[rowlist[blockIdx.x]];
     const int tc = blockIdx.y;
     const FftLen d = fv.lens[row.len];
-    const FftInner &in = fv.inner[d.inner];
     const int N = row.nphi;
     const int64_t rowF = (int64_t)tc * fv.nrings;
     const double *mp = map + (int64_t)tc * fv.npix;
-    const bool direct = d.kind == FFT_DIRECT;
-    const int *pos = fv.itab + in.pos;
-    auto rd = [&](int k) { return buf[direct ? pos[k] : k]; };
 
     if (row.mode == ROW_PAIR) {
-        for (int x = threadIdx.x; x < N; x += blockDim.x) {
+        auto xin = [&](int x) {
             double a = mp[fv.ofs[row.ya] + (int64_t)x * fv.stride];
             double b = row.yb >= 0 ? mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] : 0.0;
-            buf[x] = make_double2(a, b);
-        }
-        __syncthreads();
-        if (direct) fft_dif(buf, in, true, fv.ctab);
-        else bluestein<NREG>(buf, fv, d, true);
+            return make_double2(a, b);
+        };
+        const SpecRead<MODE> rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
         for (int side = 0; side < (row.yb >= 0 ? 2 : 1); ++side) {
             const int y = side ? row.yb : row.ya;
             const int mv = min(fv.mvalid[y], fv.mmax);
@@ -442,14 +645,12 @@ __global__ __launch_bounds__(512) void k_ring_anal(FftView fv, const int *__rest
         }
     } else {
         const int h = N / 2;
-        for (int n = threadIdx.x; n < h; n += blockDim.x) {
+        auto xin = [&](int n) {
             double a = mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride];
             double b = mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride];
-            buf[n] = make_double2(a, b);
-        }
-        __syncthreads();
-        if (direct) fft_dif(buf, in, true, fv.ctab);
-        else bluestein<NREG>(buf, fv, d, true);
+            return make_double2(a, b);
+        };
+        const SpecRead<MODE> rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
         const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}, k < h
         const int y = row.ya;
         const int mv = min(fv.mvalid[y], fv.mmax);
@@ -479,6 +680,7 @@ __global__ __launch_bounds__(512) void k_ring_anal(FftView fv, const int *__rest
 
 // Bluestein kernel spectra: Bhat = FFT_M(b) / M, b_j = conj(w_j) for |j| < L
 // (w for the given sign), stored in the inner transform's digit-reversed order.
+template <bool POW2>
 __global__ __launch_bounds__(512) void k_blue_prep(FftView fv, int len_id, int fwd_sign,
                                                    double2 *out)
 {
@@ -497,26 +699,45 @@ __global__ __launch_bounds__(512) void k_blue_prep(FftView fv, int len_id, int f
     };
     const double invM = 1.0 / (double)M;
     if (d.kind == FFT_BLUE) {
-        for (int j = threadIdx.x; j < M; j += blockDim.x) buf[j] = bval(j);
+        for (int j = threadIdx.x; j < M; j += blockDim.x) buf[PADI(j)] = bval(j);
         __syncthreads();
-        fft_dif(buf, in, true, fv.ctab);
+        fft_dif<POW2>(buf, in, true, fv.ctab);
         for (int p = threadIdx.x; p < M; p += blockDim.x)
-            out[p] = make_double2(buf[p].x * invM, buf[p].y * invM);
+            out[p] = make_double2(buf[PADI(p)].x * invM, buf[PADI(p)].y * invM);
     } else {
         const int Mh = M / 2;
         const double2 *wm = fv.ctab + d.wm;
         for (int half = 0; half < 2; ++half) {
             for (int j = threadIdx.x; j < Mh; j += blockDim.x) {
                 double2 a = bval(j), b = bval(j + Mh);
-                buf[j] = half ? cmul(csub(a, b), wm[j]) : cadd(a, b);
+                buf[PADI(j)] = half ? cmul(csub(a, b), wm[j]) : cadd(a, b);
             }
             __syncthreads();
-            fft_dif(buf, in, true, fv.ctab);
+            fft_dif<POW2>(buf, in, true, fv.ctab);
             for (int p = threadIdx.x; p < Mh; p += blockDim.x)
-                out[half * Mh + p] = make_double2(buf[p].x * invM, buf[p].y * invM);
+                out[half * Mh + p] = make_double2(buf[PADI(p)].x * invM, buf[PADI(p)].y * invM);
             __syncthreads();
         }
     }
+}
+
+// Rader kernel spectra: Bhat = FFT_{L-1}(b) / (L-1) with b_q = w^{g^{-q}},
+// w = e^{+2 pi i / L} (minus = 0) or its conjugate, in the inner transform's
+// digit-reversed order.
+template <bool POW2>
+__global__ __launch_bounds__(512) void k_rader_prep(FftView fv, int len_id, int minus, double2 *out)
+{
+    extern __shared__ double2 buf[];
+    const FftLen d = fv.lens[len_id];
+    const FftInner &in = fv.inner[d.inner];
+    const double2 *bq = fv.ctab + d.chirp;
+    const int Lm = d.L - 1;
+    for (int q = threadIdx.x; q < Lm; q += blockDim.x) buf[PADI(q)] = minus ? cconj(bq[q]) : bq[q];
+    __syncthreads();
+    fft_dif<POW2>(buf, in, true, fv.ctab);
+    const double inv = 1.0 / (double)Lm;
+    for (int p = threadIdx.x; p < Lm; p += blockDim.x)
+        out[p] = make_double2(buf[PADI(p)].x * inv, buf[PADI(p)].y * inv);
 }
 
 // ------------------------------------------------------------------ host
@@ -533,6 +754,46 @@ static bool factor_smooth(int n, std::vector<int> &rad)
         while (m % r == 0) { rad.push_back(r); m /= r; }
     if (m == 8) rad.push_back(8), m = 1;
     return m == 1 && (int)rad.size() <= FFT_MAXRAD;
+}
+
+static bool is_prime(int n)
+{
+    if (n < 2) return false;
+    for (int d = 2; (int64_t)d * d <= n; ++d)
+        if (n % d == 0) return false;
+    return true;
+}
+
+static int64_t powmod(int64_t b, int64_t e, int64_t m)
+{
+    int64_t r = 1;
+    b %= m;
+    while (e) {
+        if (e & 1) r = r * b % m;
+        b = b * b % m;
+        e >>= 1;
+    }
+    return r;
+}
+
+// smallest generator of the multiplicative group modulo the prime p
+static int primitive_root(int p)
+{
+    std::vector<int> fac;
+    int m = p - 1;
+    for (int d = 2; d * d <= m; ++d)
+        if (m % d == 0) {
+            fac.push_back(d);
+            while (m % d == 0) m /= d;
+        }
+    if (m > 1) fac.push_back(m);
+    for (int g = 2; g < p; ++g) {
+        bool ok = true;
+        for (int q : fac)
+            if (powmod(g, (p - 1) / q, p) == 1) { ok = false; break; }
+        if (ok) return g;
+    }
+    return 1;   // p = 2
 }
 
 struct FftHost {
@@ -592,7 +853,7 @@ static int lds_limit_complex()
         bytes = 65536;
     }
     int c = 1;
-    while (c * 2 * 16 <= bytes) c *= 2;
+    while (lds_padded(c * 2) * 16 <= bytes) c *= 2;
     return c;
 }
 
@@ -608,6 +869,28 @@ static int add_len(FftHost &H, int L, int cmax, int &err)
         d.M = L;
         d.inner = add_inner(H, L);
         d.lds_complex = L;
+    } else if (L > 2 && L <= cmax && L - 1 <= FFT_NREG * 1024 && is_prime(L) &&
+               factor_smooth(L - 1, rad)) {
+        d.kind = FFT_RADER;
+        d.M = L - 1;
+        d.inner = add_inner(H, L - 1);
+        d.lds_complex = L;       // the natural-order input before the reordering
+        const int g = primitive_root(L);
+        const int ginv = (int)powmod(g, L - 2, L);
+        d.gpow = (int64_t)H.itab.size();
+        for (int64_t p = 0, v = 1; p < L - 1; ++p, v = v * g % L) H.itab.push_back((int)v);
+        d.qpos = (int64_t)H.itab.size();
+        H.itab.resize(H.itab.size() + L, 0);
+        d.chirp = (int64_t)H.ctab.size();
+        for (int64_t q = 0, v = 1; q < L - 1; ++q, v = v * ginv % L) {
+            H.itab[d.qpos + v] = (int)q;           // g^{-q} = v
+            const long double a = 2.0L * kPi * (long double)v / (long double)L;
+            H.ctab.push_back(make_double2((double)cosl(a), (double)sinl(a)));
+        }
+        d.bhat_p = (int64_t)H.ctab.size();
+        H.ctab.resize(H.ctab.size() + (L - 1));
+        d.bhat_m = (int64_t)H.ctab.size();
+        H.ctab.resize(H.ctab.size() + (L - 1));
     } else {
         int M = 1;
         while (M < 2 * L - 1) M *= 2;
@@ -660,12 +943,21 @@ static int64_t add_half_tw(FftHost &H, int N)
     return o;
 }
 
-// launch groups: rows sharing LDS size class and register class
+// launch groups: rows sharing LDS size class, kernel mode and radix class
 struct FftGroup {
-    int lds_complex;
-    int nreg;      // 0: no split rows; else registers per thread
+    int lds_complex;   // power of two >= every row's LDS need
+    int mode;          // KMODE_*
+    bool pow2;         // inner length a power of two
     std::vector<int> rows;
 };
+
+// threads per work group; split and Rader modes need FFT_NREG * threads >= lds_complex
+static int threads_for(const FftGroup &gr)
+{
+    if (gr.lds_complex >= 8192) return 1024;
+    if (gr.lds_complex >= 2048) return 512;
+    return 256;
+}
 
 struct FftDev {
     FftInner *inner = nullptr;
@@ -707,10 +999,11 @@ static FftView view_of(const Plan &p, const FftDev &D)
     return v;
 }
 
-static int nreg_class(int lds_complex, bool split)
+static int mode_of(const FftLen &d)
 {
-    if (!split) return 0;
-    return (lds_complex + 511) / 512;
+    if (d.kind == FFT_BLUE_SPLIT) return KMODE_SPLIT;
+    if (d.kind == FFT_RADER) return KMODE_RADER;
+    return KMODE_LDS;
 }
 
 int fft_plan_build(Plan &p)
@@ -777,25 +1070,28 @@ int fft_plan_build(Plan &p)
                 make_double2((double)cosl(64.0L * j * ph), (double)sinl(64.0L * j * ph));
     }
     // groups by LDS class
-    std::map<std::pair<int, int>, int> gid;
+    std::map<std::tuple<int, int, int>, int> gid;
     FftDev *D = new FftDev();
     for (int i = 0; i < (int)H.rows.size(); ++i) {
         const FftLen &d = H.lens[H.rows[i].len];
         int c = 256;
         while (c < d.lds_complex) c *= 2;
-        const int nreg = nreg_class(d.lds_complex, d.kind == FFT_BLUE_SPLIT);
-        auto key = std::make_pair(c, nreg);
+        const int mode = mode_of(d);
+        const int n_in = H.inner[d.inner].n;
+        const bool pow2 = (n_in & (n_in - 1)) == 0;
+        auto key = std::make_tuple(c, mode, (int)pow2);
         auto it = gid.find(key);
         if (it == gid.end()) {
             gid[key] = (int)D->groups.size();
-            D->groups.push_back(FftGroup{c, nreg, {}});
+            D->groups.push_back(FftGroup{c, mode, pow2, {}});
             it = gid.find(key);
         }
         D->groups[it->second].rows.push_back(i);
     }
     for (auto &gr : D->groups)
-        if (gr.nreg > 16) {
-            set_error("split FFT needs %d registers per thread (max 16)", gr.nreg);
+        if (gr.mode != KMODE_LDS && FFT_NREG * threads_for(gr) < gr.lds_complex) {
+            set_error("FFT of %d complex points exceeds the register slots of its work group",
+                      gr.lds_complex);
             delete D;
             return SHT_EUNSUPPORTED;
         }
@@ -834,14 +1130,34 @@ int fft_plan_build(Plan &p)
     for (int li = 0; li < (int)H.lens.size(); ++li) {
         const FftLen &d = H.lens[li];
         if (d.kind == FFT_DIRECT) continue;
-        const size_t lds = (size_t)d.lds_complex * sizeof(double2);
+        if (d.kind == FFT_RADER) {
+            const int n_in = H.inner[d.inner].n;
+            const bool pow2 = (n_in & (n_in - 1)) == 0;
+            const void *fn = pow2 ? (const void *)k_rader_prep<true> : (const void *)k_rader_prep<false>;
+            const size_t lds = (size_t)lds_padded(d.lds_complex) * sizeof(double2);
+            if (lds > 65536)
+                if ((rc = check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                        (int)lds),
+                                    "fft LDS attribute")))
+                    return rc;
+            if (pow2) {
+                hipLaunchKernelGGL(k_rader_prep<true>, dim3(1), dim3(512), lds, 0, v, li, 0, D->ctab + d.bhat_p);
+                hipLaunchKernelGGL(k_rader_prep<true>, dim3(1), dim3(512), lds, 0, v, li, 1, D->ctab + d.bhat_m);
+            } else {
+                hipLaunchKernelGGL(k_rader_prep<false>, dim3(1), dim3(512), lds, 0, v, li, 0, D->ctab + d.bhat_p);
+                hipLaunchKernelGGL(k_rader_prep<false>, dim3(1), dim3(512), lds, 0, v, li, 1, D->ctab + d.bhat_m);
+            }
+            continue;
+        }
+        // the inner length of a Bluestein transform is a power of two
+        const size_t lds = (size_t)lds_padded(d.lds_complex) * sizeof(double2);
         if (lds > 65536)
-            if ((rc = check_hip(hipFuncSetAttribute((const void *)k_blue_prep,
+            if ((rc = check_hip(hipFuncSetAttribute((const void *)k_blue_prep<true>,
                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                                 "fft LDS attribute")))
                 return rc;
-        hipLaunchKernelGGL(k_blue_prep, dim3(1), dim3(512), lds, 0, v, li, 0, D->ctab + d.bhat_p);
-        hipLaunchKernelGGL(k_blue_prep, dim3(1), dim3(512), lds, 0, v, li, 1, D->ctab + d.bhat_m);
+        hipLaunchKernelGGL(k_blue_prep<true>, dim3(1), dim3(512), lds, 0, v, li, 0, D->ctab + d.bhat_p);
+        hipLaunchKernelGGL(k_blue_prep<true>, dim3(1), dim3(512), lds, 0, v, li, 1, D->ctab + d.bhat_m);
     }
     if ((rc = check_hip(hipGetLastError(), "bluestein preparation"))) return rc;
     if ((rc = check_hip(hipDeviceSynchronize(), "bluestein preparation"))) return rc;
@@ -860,37 +1176,35 @@ void fft_plan_free(FftPlan &f)
     f.d_rows = nullptr;
 }
 
-template <int NREG>
+template <int MODE, bool POW2>
 static int launch_group_synth(const FftView &v, const FftGroup &gr, const int *rows,
                               const double *phase, double *map, int ntc, hipStream_t s)
 {
-    const size_t lds = (size_t)gr.lds_complex * sizeof(double2);
+    const size_t lds = (size_t)lds_padded(gr.lds_complex) * sizeof(double2);
     if (lds > 65536) {
-        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_synth<NREG>,
+        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_synth<MODE, POW2>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                            "fft LDS attribute");
         if (rc) return rc;
     }
-    const int nt = gr.lds_complex >= 4096 ? 512 : 256;
-    hipLaunchKernelGGL(k_ring_synth<NREG>, dim3((unsigned)gr.rows.size(), (unsigned)ntc), dim3(nt), lds,
-                       s, v, rows, phase, map);
+    hipLaunchKernelGGL((k_ring_synth<MODE, POW2>), dim3((unsigned)gr.rows.size(), (unsigned)ntc),
+                       dim3(threads_for(gr)), lds, s, v, rows, phase, map);
     return SHT_OK;
 }
 
-template <int NREG>
+template <int MODE, bool POW2>
 static int launch_group_anal(const FftView &v, const FftGroup &gr, const int *rows, const double *map,
                              double *phase, int ntc, int usew, hipStream_t s)
 {
-    const size_t lds = (size_t)gr.lds_complex * sizeof(double2);
+    const size_t lds = (size_t)lds_padded(gr.lds_complex) * sizeof(double2);
     if (lds > 65536) {
-        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_anal<NREG>,
+        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_anal<MODE, POW2>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                            "fft LDS attribute");
         if (rc) return rc;
     }
-    const int nt = gr.lds_complex >= 4096 ? 512 : 256;
-    hipLaunchKernelGGL(k_ring_anal<NREG>, dim3((unsigned)gr.rows.size(), (unsigned)ntc), dim3(nt), lds,
-                       s, v, rows, map, phase, usew);
+    hipLaunchKernelGGL((k_ring_anal<MODE, POW2>), dim3((unsigned)gr.rows.size(), (unsigned)ntc),
+                       dim3(threads_for(gr)), lds, s, v, rows, map, phase, usew);
     return SHT_OK;
 }
 
@@ -901,9 +1215,14 @@ int launch_ring_synth(const Plan &p, const double *phase, double *map, hipStream
     const int ntc = p.ntrans * p.ncomp;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
+        const int *rows = D->group_rows[i];
         int rc;
-        if (gr.nreg == 0) rc = launch_group_synth<1>(v, gr, D->group_rows[i], phase, map, ntc, s);
-        else rc = launch_group_synth<16>(v, gr, D->group_rows[i], phase, map, ntc, s);
+        // split Bluestein always has a power-of-two inner length
+        if (gr.mode == KMODE_SPLIT) rc = launch_group_synth<KMODE_SPLIT, true>(v, gr, rows, phase, map, ntc, s);
+        else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_synth<KMODE_RADER, true>(v, gr, rows, phase, map, ntc, s);
+        else if (gr.mode == KMODE_RADER) rc = launch_group_synth<KMODE_RADER, false>(v, gr, rows, phase, map, ntc, s);
+        else if (gr.pow2) rc = launch_group_synth<KMODE_LDS, true>(v, gr, rows, phase, map, ntc, s);
+        else rc = launch_group_synth<KMODE_LDS, false>(v, gr, rows, phase, map, ntc, s);
         if (rc) return rc;
     }
     return check_hip(hipGetLastError(), "ring synthesis launch");
@@ -914,11 +1233,16 @@ int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_w
     const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
     const FftView v = view_of(p, *D);
     const int ntc = p.ntrans * p.ncomp;
+    const int uw = use_weights ? 1 : 0;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
+        const int *rows = D->group_rows[i];
         int rc;
-        if (gr.nreg == 0) rc = launch_group_anal<1>(v, gr, D->group_rows[i], map, phase, ntc, use_weights, s);
-        else rc = launch_group_anal<16>(v, gr, D->group_rows[i], map, phase, ntc, use_weights, s);
+        if (gr.mode == KMODE_SPLIT) rc = launch_group_anal<KMODE_SPLIT, true>(v, gr, rows, map, phase, ntc, uw, s);
+        else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_anal<KMODE_RADER, true>(v, gr, rows, map, phase, ntc, uw, s);
+        else if (gr.mode == KMODE_RADER) rc = launch_group_anal<KMODE_RADER, false>(v, gr, rows, map, phase, ntc, uw, s);
+        else if (gr.pow2) rc = launch_group_anal<KMODE_LDS, true>(v, gr, rows, map, phase, ntc, uw, s);
+        else rc = launch_group_anal<KMODE_LDS, false>(v, gr, rows, map, phase, ntc, uw, s);
         if (rc) return rc;
     }
     return check_hip(hipGetLastError(), "ring analysis launch");

@@ -114,6 +114,20 @@ def gauss_geometry(nrings: int, nphi: int, phi0: float = 0.0) -> Geometry:
                     _packed_offsets(nph))
 
 
+def mixed_geometry(nphi_north, phi0: float = 0.0) -> Geometry:
+    """Gauss-Legendre colatitudes for 2 * len(nphi_north) rings with per-ring
+    pixel counts: ring i of the north half and its southern mirror both get
+    nphi_north[i] pixels (so that FFT lengths of every kind can be mixed in
+    one grid).  phi0 grows by phi0 per ring."""
+    nh = len(nphi_north)
+    g = gauss_geometry(2 * nh, 1)
+    nph = np.asarray(list(nphi_north) + list(nphi_north)[::-1], dtype=np.int64)
+    wgl = g.weight * (2.0 * math.pi) ** -1       # back to the GL weights (nphi = 1)
+    weight = wgl * (2.0 * math.pi / nph)
+    ph = phi0 * np.arange(2 * nh, dtype=np.float64)
+    return Geometry(g.theta, nph, ph, weight, _packed_offsets(nph))
+
+
 def healpix_geometry(nside: int) -> Geometry:
     """HEALPix ring-scheme geometry (pixel order within a ring as in HEALPix)."""
     nr = 4 * nside - 1

@@ -5,6 +5,7 @@ Tolerance for the FP64 path: normwise max relative error <= 1e-11
 (lambda_mm inherits a relative error ~ m * eps from the rounding of sin theta).
 """
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -35,6 +36,16 @@ CASES = {
     "hp_s0_j9": (lambda: si.healpix_geometry(16), 47, 47, 0, 9),
     "gl_odd_nphi_prime": (lambda: si.gauss_geometry(40, 79), 39, 39, 0, 2),
     "gl_s2_j16": (lambda: si.gauss_geometry(16, 31), 15, 15, 2, 16),
+    # ring lengths of every FFT kind: 8191 prime with 8190 = 2 3^2 5 7 13
+    # (paired, Rader), 16382 (half length 8191, Rader), 8190 (half 4095 =
+    # 3^2 5 7 13, direct), 1287 = 3^2 11 13 (paired, direct odd radices), 2006
+    # (half 1003 = 17 59, Bluestein in LDS), 4097 = 17 241 (paired, Bluestein
+    # split in two halves), 257 (prime, Rader with a power-of-two inner length),
+    # 4096 (half 2048, radix 8/4/2)
+    "fft_lengths_s2": (lambda: si.mixed_geometry([8191, 16382, 8190, 1287, 2006], 0.2),
+                       60, 60, 2, 2),
+    "fft_lengths_s0": (lambda: si.mixed_geometry([4097, 1287, 257, 2006, 4096, 8191], 0.37),
+                       45, 40, 0, 3),
 }
 
 
@@ -44,7 +55,7 @@ def _setup(name, precision="fp64"):
     g = build()
     geom = sht.Geometry.from_inputs(g)
     plan = sht.Plan(geom, lmax, mmax, spin=spin, ntrans=ntrans, precision=precision)
-    a = si.random_alm(lmax, mmax, ntrans, spin, tag=hash(name) % 1000)
+    a = si.random_alm(lmax, mmax, ntrans, spin, tag=zlib.crc32(name.encode()) % 1000)
     return g, plan, a
 
 
