@@ -15,8 +15,11 @@ SOURCES = ["sht_api.cpp", "legendre.hip", "ringfft.hip", "batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-# packed FP32 instructions are disabled for all device code
-DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# packed FP32 instructions are disabled for all device code; matrix-core
+# accumulators are kept in ordinary VGPRs (the AGPR form made the compiler copy
+# every accumulator across the loop back-edge of the synthesis kernel)
+DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
           "-Wno-unused-result"]
 

@@ -144,16 +144,25 @@ __device__ inline Chain chain_init(const LegView &v, int m, int slot, int chain)
     return c;
 }
 
-// Per-chain step coefficients of one chunk, staged in LDS:
-// (alpha_l, +-beta_l, alpha_l +- beta_l - 2, 0) for the chain's sign.
-__device__ inline double4 chain_coef(const double4 c, bool minus)
+// Per-chain step coefficients of one degree, staged in LDS:
+// (alpha_l, +-beta_l, alpha_l +- beta_l - 2, scale * f_l) for the chain's sign;
+// the last entry turns mu into the value written out (lambda times a constant).
+__device__ inline double4 chain_coef(const double4 c, bool minus, double fs)
 {
-    return minus ? double4{c.x, -c.y, c.w, 0.0} : double4{c.x, c.y, c.z, 0.0};
+    return minus ? double4{c.x, -c.y, c.w, fs} : double4{c.x, c.y, c.z, fs};
 }
 
-// Run the recursion over the degrees lc .. lc+LC-1, writing lambda (true value
-// or 0 while the lane's scale k < 0) to out[t * stride].
-template <typename T, int LC>
+// Run the recursion over the degrees lc .. lc+LC-1, writing cf.w * mu (0 while
+// the lane's scale k < 0, and cf.w = 0 outside [l0, lmax]) to out[t * stride].
+// Row of degree offset t in the chunk: natural order, or (PSPLIT) the even
+// offsets first and then the odd ones.
+template <int LC, bool PSPLIT>
+__device__ __forceinline__ int chunk_row(int t)
+{
+    return PSPLIT ? (t & 1) * (LC / 2) + (t >> 1) : t;
+}
+
+template <typename T, int LC, bool PSPLIT = false>
 __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, bool diff, bool slow,
                                    int l0, int lc, int lmax, T *out, int stride, double thr,
                                    double down)
@@ -162,7 +171,7 @@ __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, boo
 #pragma unroll 4
         for (int t = 0; t < LC; ++t) {
             const int l = lc + t;
-            out[t * stride] = (l >= l0 && l <= lmax) ? (T)c.mu : (T)0;
+            out[chunk_row<LC, PSPLIT>(t) * stride] = (l >= l0 && l <= lmax) ? (T)(c.mu * cf[t].w) : (T)0;
             if (l >= l0 && l < lmax) {
                 const double4 q = cf[t];
                 if (diff) {
@@ -180,7 +189,8 @@ __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, boo
     } else {
         for (int t = 0; t < LC; ++t) {
             const int l = lc + t;
-            out[t * stride] = (l >= l0 && l <= lmax && c.k == 0) ? (T)c.mu : (T)0;
+            out[chunk_row<LC, PSPLIT>(t) * stride] =
+                (l >= l0 && l <= lmax && c.k == 0) ? (T)(c.mu * cf[t].w) : (T)0;
             if (l >= l0 && l < lmax) {
                 const double4 q = cf[t];
                 if (diff) {
@@ -205,15 +215,15 @@ __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, boo
 
 // Fast path of chain_chunk: every degree of the chunk lies in [l0, lmax) and
 // every lane of the wavefront already has k = 0 (no masking, no rescaling).
-template <typename T, int LC>
+template <typename T, int LC, bool PSPLIT = false>
 __device__ __forceinline__ void chain_chunk_fast(Chain &c, const double4 *__restrict__ cf, bool diff,
                                                  T *out, int stride)
 {
     if (diff) {
 #pragma unroll
         for (int t = 0; t < LC; ++t) {
-            out[t * stride] = (T)c.mu;
             const double4 q = cf[t];
+            out[chunk_row<LC, PSPLIT>(t) * stride] = (T)(c.mu * q.w);
             const double eps = fma(q.x, c.ms2, q.z);
             c.aux = fma(eps, c.mu, c.aux);
             c.mu += c.aux;
@@ -221,8 +231,8 @@ __device__ __forceinline__ void chain_chunk_fast(Chain &c, const double4 *__rest
     } else {
 #pragma unroll
         for (int t = 0; t < LC; ++t) {
-            out[t * stride] = (T)c.mu;
             const double4 q = cf[t];
+            out[chunk_row<LC, PSPLIT>(t) * stride] = (T)(c.mu * q.w);
             const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
             c.aux = c.mu;
             c.mu = nx;
@@ -238,114 +248,65 @@ __device__ __forceinline__ bool wave_any(bool p)
 // wavefronts with a slot of cos t above this use the difference form
 constexpr double DIFF_FORM_COS = 0.7;
 
-// Recursion role of a wavefront within a work group of LEG_NW = 4 wavefronts
-// covering 4 slot tiles.  Spin 0: wavefront w runs tile w (64 slots).  Spin 2:
-// wavefronts 2g and 2g+1 run the +2 and -2 chains of tiles 2g, 2g+1 (32 slots
-// each), so that every wavefront's chains share one sign.
-template <int SPIN>
-struct RecRole {
-    int tile_local;    // tile (0..3) of this lane's chain
-    int slot_local;    // slot within that tile
-    int chain;         // 0: +s, 1: -s
-    __device__ RecRole(int wave, int lane)
-    {
-        if (SPIN) {
-            tile_local = 2 * (wave >> 1) + (lane >> 5);
-            slot_local = lane & 31;
-            chain = wave & 1;
-        } else {
-            tile_local = wave;
-            slot_local = lane;
-            chain = 0;
-        }
-    }
-};
-
 // ---------------------------------------------------------------- synthesis
 
-constexpr int SYN_LC = 16;   // degrees per chunk
+constexpr int SYN_LC = 16;          // degrees per chunk
+constexpr int SYN_ROW = 64 + 8;     // LDS row of lambda: one degree, 64 chains (+ pad)
 
-// B-operand layout of a synthesis chunk (16 degrees lc .. lc+15, lc + m even).
-// Element e = ((p * KS + ks) * NCB + cb) * 64 + lane, lane = j + 16 kk, column
-// col = j + 16 cb.  Spin 0: class p, k-step ks holds the degrees
-// lc + p + 2 kk + 8 ks.  Spin 2: each k-step holds rows of one kind, so that
-// the A operand is built with the same operation in every lane:
-//   class 0: ks 0,1: W rows at lc + 8 ks + 2 kk;  ks 2,3: X rows at lc + 8 (ks-2) + 2 kk + 1
-//   class 1: ks 0,1: W rows at lc + 8 ks + 2 kk + 1;  ks 2,3: X rows at lc + 8 (ks-2) + 2 kk
-// (W rows have the parity class of l + m, X rows the opposite one).
-template <int SPIN, int NCB>
-struct SynLayout {
-    static constexpr int KS = SPIN ? 4 : 2;
-    static constexpr int NB = 2 * KS * NCB * 64;
-    // degree offset, a_lm component / re-im and sign-scale of element e; scale 0: zero
-    __device__ static inline void element(int e, int m, int t0, int ntrans, int &loff,
-                                          int &tcomp, int &reim, double &scale)
-    {
-        const int ln = e & 63;
-        const int cb = (e >> 6) % NCB;
-        const int ks = (e >> 6) / NCB % KS;
-        const int p = (e >> 6) / NCB / KS;
-        const int j = ln & 15, kk = ln >> 4;
-        const int col = j + 16 * cb;
-        if constexpr (SPIN == 0) {
-            loff = p + 2 * kk + 8 * ks;
-            const int t = t0 + (col >> 1);
-            reim = col & 1;
-            tcomp = t;
-            scale = (t < ntrans && !(m == 0 && reim)) ? 1.0 : 0.0;
-        } else {
-            const bool wrow = ks < 2;
-            const int par = (p == 0) ? (wrow ? 0 : 1) : (wrow ? 1 : 0);
-            loff = 8 * (ks & 1) + 2 * kk + par;
-            const int t = t0 + (col >> 2);
-            const int o = col & 3;
-            int comp;
-            // W row: -(E_re, E_im, B_re, B_im); X row: (B_im, -B_re, -E_im, E_re); times 1/2
-            if (wrow) {
-                comp = o >> 1;
-                reim = o & 1;
-                scale = -0.5;
-            } else {
-                comp = (o == 0 || o == 1) ? 1 : 0;
-                reim = (o == 0 || o == 2) ? 1 : 0;
-                scale = (o == 0 || o == 3) ? 0.5 : -0.5;
-            }
-            tcomp = 2 * t + comp;
-            if (t >= ntrans || (m == 0 && reim)) scale = 0.0;
-        }
-    }
-};
+// Exchange of values between lanes q and 3 - q of every group of four lanes
+// (the four columns Q_re, Q_im, U_re, U_im of one transform).
+__device__ __forceinline__ float quad_rev(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x1B, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double quad_rev(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x1B, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x1B, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
+// One wavefront per work item (m, slot tile, group of transforms); no data is
+// shared between wavefronts, so there is no work-group barrier beyond the
+// wavefront itself.
+//
+// Recursion: lane = chain * 32 + slot (spin 2: chain 0 = +2, 1 = -2) or lane =
+// slot (spin 0); each chunk of SYN_LC degrees is written to LDS as
+// c * f_l * mu_l (c = 1/2 for spin 2, 1 for spin 0).
+//
+// Products (Eq. 4) on 16x16x4 matrix-core tiles, rows = 16 slots, columns =
+// 16 of the group's (transform, component, re/im) columns, k = 4 degrees of
+// one parity class (degrees lc + 8h + 2kk + parity, lc + m even):
+//   spin 0:  A = lambda,  B = (Re a_lm, Im a_lm) per transform;
+//   spin 2:  rows W = -(lambda_+ + lambda_-)/2 and X = (lambda_+ - lambda_-)/2,
+//            B_W[o] = (E_re, E_im, B_re, B_im)[o] and B_X[o] = s_o B_W[3 - o],
+//            s = (+, -, -, +), for the columns o = (Q_re, Q_im, U_re, U_im).
+// The B operand is read from a_lm straight into registers (one chunk ahead),
+// the X form by a lane exchange inside groups of four.  Class 0 collects the
+// terms whose mirror-ring sign is +1 (W at l + m even, X at l + m odd), class
+// 1 the others; ring t gets A0 + A1, ring pi - t gets A0 - A1.
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_synth(LegView v,
-                                                                   const LegItem *__restrict__ items,
-                                                                   const double *__restrict__ alm,
-                                                                   double *__restrict__ phase,
-                                                                   int jobs_per_group, int flush_chunks)
+__global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem *__restrict__ items,
+                                                       const double *__restrict__ alm,
+                                                       double *__restrict__ phase, int flush_chunks)
 {
     using T = typename MT<F32>::T;
     using V = typename MT<F32>::V;
-    using LY = SynLayout<SPIN, NCB>;
     constexpr int SPT = SPIN ? 32 : 64;          // slots per tile
     constexpr int NSB = SPT / 16;                // 16-slot row blocks
-    constexpr int LC = SYN_LC;
-    constexpr int KS = LY::KS;
-    constexpr int NB = LY::NB;
-    constexpr int NT = 64 * LEG_NW;
-    constexpr int BPT = NB / NT;                 // fragment elements per thread
-    static_assert(NB % NT == 0, "fragment staging");
     constexpr int NCH = SPIN ? 2 : 1;
+    constexpr int LC = SYN_LC;
     constexpr int NCOMP = SPIN ? 2 : 1;
-    __shared__ T bst[2][NB];
+    constexpr int CPJ = SPIN ? 4 : 2;            // columns per transform
+    __shared__ T lam[LC][SYN_ROW];
     __shared__ double4 cfs[2][NCH][LC];
-    __shared__ T lam[LEG_NW][LC][NCH][SPT];
 
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int lane = threadIdx.x;
     const int i16 = lane & 15, kk = lane >> 4;
-    const LegItem *it = items + blockIdx.x;
-    const int m = it->m;
-    const int t0 = blockIdx.y * jobs_per_group;
+    const WaveItem it = items[blockIdx.x];
+    if (it.m < 0) return;
+    const int m = it.m, tile = it.tile, t0 = it.t0;
     const int lmax = v.lmax;
     const int l0 = m > SPIN ? m : SPIN;
     const int lstart = l0 - ((l0 + m) & 1);
@@ -353,52 +314,55 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_synth(LegView v,
     const double *flm = v.fl + v.coef_ofs[m];
     const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
     const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
+    const double fscale = SPIN ? 0.5 : 1.0;
 
     // recursion role
-    const RecRole<SPIN> rr(wave, lane);
-    const int rtile = it->tile[rr.tile_local];
-    Chain cs = chain_init(v, m, rtile >= 0 ? rtile * SPT + rr.slot_local : v.nslots, rr.chain);
+    const int rslot = SPIN ? (lane & 31) : lane;
+    const int rchain = SPIN ? (lane >> 5) : 0;
+    Chain cs = chain_init(v, m, tile * SPT + rslot, rchain);
     const bool diff = wave_any(cs.x > DIFF_FORM_COS);
     if (diff) cs.aux = cs.mu;
     bool slow = wave_any(cs.k < 0);
-    T *lam_out = &lam[rr.tile_local][0][rr.chain][rr.slot_local];
-    // product role
-    const int mtile = it->tile[wave];
-    const bool active = mtile >= 0;
-    const int slot0 = active ? mtile * SPT : 0;
 
-    // this thread's staging elements: fixed source column, degree offset, scale
-    const double *ebase[BPT];
-    int eloff[BPT];
-    double escale[BPT];
+    // B operand sources: this lane's column in each column block
+    const double *bp[NCB];
+    bool bok[NCB];
 #pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-        int loff, tcomp, reim;
-        double sc;
-        LY::element(tid + j * NT, m, t0, v.ntrans, loff, tcomp, reim, sc);
-        eloff[j] = loff;
-        escale[j] = sc;
-        ebase[j] = (sc != 0.0) ? alm + ((int64_t)tcomp * v.nalm + mbase) * 2 + reim : alm;
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int col = i16 + 16 * cb;
+        const int t = t0 + col / CPJ, o = col % CPJ;
+        const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
+        bok[cb] = t < v.ntrans && !(m == 0 && reim);
+        bp[cb] = alm + (((int64_t)(bok[cb] ? t : 0) * NCOMP + comp) * v.nalm + mbase) * 2 + reim;
     }
-    double pv[BPT];
-    double4 pc = double4{0, 0, 0, 0};
-    auto prefetch = [&](int lc) {
+    const bool xneg = SPIN && ((i16 & 3) == 1 || (i16 & 3) == 2);
+
+    // raw coefficients of a chunk: R[par][h][cb] = a(column, lc + 8h + 2kk + par)
+    double R[2][2][NCB], Rn[2][2][NCB];
+    auto loadB = [&](int lc, double (&dst)[2][2][NCB]) {
 #pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int l = lc + eloff[j];
-            const bool ok = escale[j] != 0.0 && l >= l0 && l <= lmax;
-            pv[j] = ok ? ebase[j][2 * (int64_t)l] * (escale[j] * flm[l]) : 0.0;
-        }
-        if (tid < NCH * LC) {
-            const int l = lc + (tid % LC);
+        for (int par = 0; par < 2; ++par)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const int l = lc + 8 * h + 2 * kk + par;
+                    const bool ok = bok[cb] && l >= l0 && l <= lmax;
+                    dst[par][h][cb] = ok ? bp[cb][2 * (int64_t)l] : 0.0;
+                }
+    };
+    double4 qn = double4{0, 0, 0, 0};
+    auto loadC = [&](int lc) {
+        if (lane < NCH * LC) {
+            const int t = lane % LC;
+            const int l = lc + t;
             const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
-            pc = chain_coef(c, tid >= LC);
+            const double f = (l >= l0 && l <= lmax) ? flm[l] * fscale : 0.0;
+            qn = chain_coef(c, lane >= LC, f);
         }
     };
-    auto commit = [&](int buf) {
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) bst[buf][tid + j * NT] = (T)pv[j];
-        if (tid < NCH * LC) cfs[buf][tid / LC][tid % LC] = pc;
+    auto storeC = [&](int buf) {
+        if (lane < NCH * LC) cfs[buf][lane / LC][lane % LC] = qn;
     };
 
     V acc[2][NSB][NCB];
@@ -420,79 +384,100 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_synth(LegView v,
                     for (int r = 0; r < 4; ++r) acc64[p][sb][cb][r] = 0.0;
     }
 
-    prefetch(lstart);
-    commit(0);
+    loadB(lstart, R);
+    loadC(lstart);
+    storeC(0);
     __syncthreads();
     int chunk = 0;
     for (int lc = lstart; lc <= lmax; lc += LC, ++chunk) {
         const int buf = chunk & 1;
         const bool more = lc + LC <= lmax;
-        if (more) prefetch(lc + LC);
-        if (rtile >= 0 || !SPIN) {
-            if (!slow && lc >= l0 && lc + LC <= lmax) {
-                chain_chunk_fast<T, LC>(cs, cfs[buf][rr.chain], diff, lam_out, NCH * SPT);
-            } else {
-                chain_chunk<T, LC>(cs, cfs[buf][rr.chain], diff, slow, l0, lc, lmax, lam_out,
-                                   NCH * SPT, thr, down);
-                slow = wave_any(cs.k < 0);
-            }
+        if (more) {
+            loadB(lc + LC, Rn);
+            loadC(lc + LC);
+        }
+        T *out = &lam[0][lane];
+        if (!slow && lc >= l0 && lc + LC <= lmax) {
+            chain_chunk_fast<T, LC>(cs, cfs[buf][rchain], diff, out, SYN_ROW);
+        } else {
+            chain_chunk<T, LC>(cs, cfs[buf][rchain], diff, slow, l0, lc, lmax, out, SYN_ROW, thr, down);
+            slow = wave_any(cs.k < 0);
         }
         __syncthreads();
-        if (active) {
-            const T *bb = bst[buf];
-            if constexpr (SPIN == 0) {
+        if constexpr (SPIN == 0) {
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
+            for (int h = 0; h < 2; ++h) {
+                T b0[NCB], b1[NCB];
 #pragma unroll
-                    for (int sb = 0; sb < NSB; ++sb) {
-                        const T a0 = lam[wave][0 + 2 * kk + 8 * ks][0][sb * 16 + i16];
-                        const T a1 = lam[wave][1 + 2 * kk + 8 * ks][0][sb * 16 + i16];
+                for (int cb = 0; cb < NCB; ++cb) {
+                    b0[cb] = (T)R[0][h][cb];
+                    b1[cb] = (T)R[1][h][cb];
+                }
 #pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb) {
-                            acc[0][sb][cb] = mfma(a0, bb[((0 * KS + ks) * NCB + cb) * 64 + lane], acc[0][sb][cb]);
-                            acc[1][sb][cb] = mfma(a1, bb[((1 * KS + ks) * NCB + cb) * 64 + lane], acc[1][sb][cb]);
-                        }
+                for (int sb = 0; sb < NSB; ++sb) {
+                    const T a0 = lam[8 * h + 2 * kk][sb * 16 + i16];
+                    const T a1 = lam[8 * h + 2 * kk + 1][sb * 16 + i16];
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        acc[0][sb][cb] = mfma(a0, b0[cb], acc[0][sb][cb]);
+                        acc[1][sb][cb] = mfma(a1, b1[cb], acc[1][sb][cb]);
                     }
-            } else {
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int sb = 0; sb < NSB; ++sb) {
-                        const int te = 8 * h + 2 * kk;
-                        const T upe = lam[wave][te][0][sb * 16 + i16];
-                        const T ume = lam[wave][te][1][sb * 16 + i16];
-                        const T upo = lam[wave][te + 1][0][sb * 16 + i16];
-                        const T umo = lam[wave][te + 1][1][sb * 16 + i16];
-                        const T we = upe + ume, xe = upe - ume;
-                        const T wo = upo + umo, xo = upo - umo;
-#pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb) {
-                            acc[0][sb][cb] = mfma(we, bb[((0 * KS + h) * NCB + cb) * 64 + lane], acc[0][sb][cb]);
-                            acc[0][sb][cb] = mfma(xo, bb[((0 * KS + 2 + h) * NCB + cb) * 64 + lane], acc[0][sb][cb]);
-                            acc[1][sb][cb] = mfma(wo, bb[((1 * KS + h) * NCB + cb) * 64 + lane], acc[1][sb][cb]);
-                            acc[1][sb][cb] = mfma(xe, bb[((1 * KS + 2 + h) * NCB + cb) * 64 + lane], acc[1][sb][cb]);
-                        }
-                    }
+                }
             }
-            if constexpr (F32) {
-                if ((chunk + 1) % flush_chunks == 0) {
+        } else {
 #pragma unroll
-                    for (int p = 0; p < 2; ++p)
+            for (int h = 0; h < 2; ++h) {
+                T bwe[NCB], bwo[NCB], bxe[NCB], bxo[NCB];
 #pragma unroll
-                        for (int sb = 0; sb < NSB; ++sb)
+                for (int cb = 0; cb < NCB; ++cb) {
+                    bwe[cb] = (T)R[0][h][cb];
+                    bwo[cb] = (T)R[1][h][cb];
+                    const T xe = quad_rev(bwe[cb]), xo = quad_rev(bwo[cb]);
+                    bxe[cb] = xneg ? -xe : xe;
+                    bxo[cb] = xneg ? -xo : xo;
+                }
 #pragma unroll
-                            for (int cb = 0; cb < NCB; ++cb) {
+                for (int sb = 0; sb < NSB; ++sb) {
+                    const int te = 8 * h + 2 * kk;
+                    const T upe = lam[te][sb * 16 + i16], ume = lam[te][32 + sb * 16 + i16];
+                    const T upo = lam[te + 1][sb * 16 + i16], umo = lam[te + 1][32 + sb * 16 + i16];
+                    const T awe = -(upe + ume), axe = upe - ume;
+                    const T awo = -(upo + umo), axo = upo - umo;
 #pragma unroll
-                                for (int r = 0; r < 4; ++r) acc64[p][sb][cb][r] += (double)acc[p][sb][cb][r];
-                                acc[p][sb][cb] = V{0, 0, 0, 0};
-                            }
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        acc[0][sb][cb] = mfma(awe, bwe[cb], acc[0][sb][cb]);
+                        acc[0][sb][cb] = mfma(axo, bxo[cb], acc[0][sb][cb]);
+                        acc[1][sb][cb] = mfma(awo, bwo[cb], acc[1][sb][cb]);
+                        acc[1][sb][cb] = mfma(axe, bxe[cb], acc[1][sb][cb]);
+                    }
                 }
             }
         }
-        if (more) commit(buf ^ 1);
+        if constexpr (F32) {
+            if ((chunk + 1) % flush_chunks == 0) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) acc64[p][sb][cb][r] += (double)acc[p][sb][cb][r];
+                            acc[p][sb][cb] = V{0, 0, 0, 0};
+                        }
+            }
+        }
+        if (more) {
+            storeC(buf ^ 1);
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) R[par][h][cb] = Rn[par][h][cb];
+        }
         __syncthreads();
     }
-    if (!active) return;
 
     // epilogue: ring t = A0 + A1, ring pi - t = A0 - A1
 #pragma unroll
@@ -510,20 +495,12 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_synth(LegView v,
                     c1 = acc[1][sb][cb][r];
                 }
                 const int row = c_row<F32>(lane, r);
-                const int slot = slot0 + sb * 16 + row;
+                const int slot = tile * SPT + sb * 16 + row;
                 if (slot >= v.nslots) continue;
                 const int col = i16 + 16 * cb;
-                int t, comp, reim;
-                if constexpr (SPIN == 0) {
-                    t = t0 + (col >> 1);
-                    comp = 0;
-                    reim = col & 1;
-                } else {
-                    t = t0 + (col >> 2);
-                    comp = (col & 3) >> 1;
-                    reim = col & 1;
-                }
+                const int t = t0 + col / CPJ, o = col % CPJ;
                 if (t >= v.ntrans) continue;
+                const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                 const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
                 const int64_t rowbase = ((int64_t)t * NCOMP + comp) * v.nrings;
                 if (yn >= 0) phase[((rowbase + yn) * (v.mmax + 1) + m) * 2 + reim] = c0 + c1;
@@ -535,6 +512,24 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_synth(LegView v,
 
 constexpr int ANA_LC = 32;   // degrees per chunk (16 per parity class)
 
+// Orders the LDS traffic of one wavefront at this point (the LDS executes a
+// wavefront's requests in issue order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Work group = one m and a group of transforms.  The m's active slot tiles are
+// taken LEG_NW at a time (one per wavefront).  Each wavefront runs the
+// recursion of its own tile (lane = chain * 32 + slot, or slot) into its own
+// LDS region, multiplies lambda^T (16 degrees of one parity x 4 slots) with
+// the tile's phases held in registers as G_t +- G_(pi-t) on 16x16x4 matrix-core
+// tiles, and leaves its partial sums in the same region; after one work-group
+// barrier the partial sums of the wavefronts are added in a fixed order and
+// accumulated into a_lm (deterministic, no atomics).
 template <int SPIN, int NCB, bool F32>
 __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
                                                                   const double *__restrict__ phase,
@@ -554,14 +549,13 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
     constexpr int NCOL = NCB * 16;
     constexpr int NOUT = LC * NCOL;    // output elements per chunk
     constexpr int OPT = (NOUT + NT - 1) / NT;
-    constexpr int LAMW = NCH * LC * LDP;   // lambda elements per tile
-    // lambda tiles and, once the products are done, the partial sums share LDS
-    constexpr int LAM_BYTES = LEG_NW * LAMW * (int)sizeof(T);
-    constexpr int PART_BYTES = LEG_NW * NOUT * (int)sizeof(double);
-    constexpr int SMEM_D = ((LAM_BYTES > PART_BYTES ? LAM_BYTES : PART_BYTES) + 7) / 8;
-    __shared__ double smem[SMEM_D];
-    __shared__ double4 cfs[NCH][LC];
-    __shared__ double fls[LC];
+    constexpr int LAMW = NCH * LC * LDP;   // lambda elements per wavefront
+    // per wavefront: lambda [chain][row][LDP] (rows: even degree offsets, then
+    // odd ones), reused for the wavefront's partial sums once its products are done
+    constexpr int REG_B = LAMW * (int)sizeof(T) > NOUT * 8 ? LAMW * (int)sizeof(T) : NOUT * 8;
+    constexpr int REG_D = (REG_B + 7) / 8;
+    __shared__ double smem[LEG_NW * REG_D];
+    __shared__ double4 cfs[LEG_NW][NCH][LC];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -575,11 +569,11 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
     const double *flm = v.fl + v.coef_ofs[m];
     const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
     const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
-    T *lamb = reinterpret_cast<T *>(smem);          // [tile][chain][LC][LDP]
-    double *part = smem;                            // [LEG_NW][NOUT] after the products
-    const RecRole<SPIN> rr(wave, lane);
-    T *lam_out = lamb + (rr.tile_local * NCH + rr.chain) * LC * LDP + rr.slot_local;
-    const T *lam_mine = lamb + wave * LAMW;
+    T *lam_w = reinterpret_cast<T *>(smem + wave * REG_D);
+    double *part_w = smem + wave * REG_D;
+    const int rslot = SPIN ? (lane & 31) : lane;
+    const int rchain = SPIN ? (lane >> 5) : 0;
+    T *lam_out = lam_w + rchain * LC * LDP + rslot;
 
     // this thread's output elements of a chunk: element e -> (transform, component,
     // degree offset, re/im), consecutive e consecutive in memory
@@ -612,19 +606,18 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
     int tcount = 0, tscan = 0;
     bool first = true;
     while (tcount < ntiles_act || first) {
-        int ptile_r = -1, ptile_m = -1;    // tiles of this wave's recursion and product roles
+        int ptile = -1;    // this wavefront's tile in this pass
         {
             int k = 0;
             for (; tscan < v.ntiles && k < LEG_NW; ++tscan) {
                 if (v.tile_mlim[tscan] < m) continue;
-                if (k == rr.tile_local) ptile_r = tscan;
-                if (k == wave) ptile_m = tscan;
+                if (k == wave) ptile = tscan;
                 ++k;
             }
             tcount += k;
         }
-        const bool active = ptile_m >= 0;
-        const int slot0 = active ? ptile_m * SPT : 0;
+        const bool active = ptile >= 0;
+        const int slot0 = active ? ptile * SPT : 0;
         // stationary phase fragments B[kk][j] for slot 4 ks + kk and column j + 16 cb:
         // gw[q] multiplies W (spin 2) or lambda (spin 0) rows, gx[q] the X rows;
         // q = 0: G_t + G_(pi-t), q = 1: G_t - G_(pi-t).  For output o the X part
@@ -668,21 +661,12 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                 }
             }
         }
-        Chain cs = chain_init(v, m, ptile_r >= 0 ? ptile_r * SPT + rr.slot_local : v.nslots, rr.chain);
+        Chain cs = chain_init(v, m, active ? ptile * SPT + rslot : v.nslots, rchain);
         const bool diff = wave_any(cs.x > DIFF_FORM_COS);
         if (diff) cs.aux = cs.mu;
         bool slow = wave_any(cs.k < 0);
         for (int lc = lstart; lc <= lmax; lc += LC) {
             double pold[OPT];
-            if (tid < NCH * LC) {
-                const int l = lc + (tid % LC);
-                const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
-                cfs[tid / LC][tid % LC] = chain_coef(c, tid >= LC);
-            }
-            if (tid < LC) {
-                const int l = lc + tid;
-                fls[tid] = (l >= l0 && l <= lmax) ? flm[l] : 0.0;
-            }
             if (!first) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
@@ -690,34 +674,39 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                     pold[j] = (l >= l0 && l <= lmax) ? obase[j][2 * (int64_t)l] : 0.0;
                 }
             }
-            __syncthreads();
-            if (ptile_r >= 0 || !SPIN) {
-                if (!slow && lc >= l0 && lc + LC <= lmax) {
-                    chain_chunk_fast<T, LC>(cs, cfs[rr.chain], diff, lam_out, LDP);
-                } else {
-                    chain_chunk<T, LC>(cs, cfs[rr.chain], diff, slow, l0, lc, lmax, lam_out, LDP, thr, down);
-                    slow = wave_any(cs.k < 0);
-                }
-            }
-            __syncthreads();
             V acc[2][NCB];   // [class][column block]
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = V{0, 0, 0, 0};
             if (active) {
+                if (lane < NCH * LC) {
+                    const int l = lc + (lane % LC);
+                    const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
+                    const double f = (l >= l0 && l <= lmax) ? flm[l] * (SPIN ? 0.5 : 1.0) : 0.0;
+                    cfs[wave][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
+                }
+                wave_sync();
+                if (!slow && lc >= l0 && lc + LC <= lmax) {
+                    chain_chunk_fast<T, LC, true>(cs, cfs[wave][rchain], diff, lam_out, LDP);
+                } else {
+                    chain_chunk<T, LC, true>(cs, cfs[wave][rchain], diff, slow, l0, lc, lmax, lam_out, LDP,
+                                             thr, down);
+                    slow = wave_any(cs.k < 0);
+                }
+                wave_sync();
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
 #pragma unroll
                     for (int ks = 0; ks < KSA; ++ks) {
-                        // A[i][kk] = Lambda[degree lc + p + 2 i][slot 4 ks + kk]
+                        // A[i][kk] = Lambda[degree lc + p + 2 i][slot 4 ks + kk] (rows split by parity)
                         if constexpr (SPIN == 0) {
-                            const T a = lam_mine[(p + 2 * i16) * LDP + 4 * ks + kk];
+                            const T a = lam_w[(p * (LC / 2) + i16) * LDP + 4 * ks + kk];
 #pragma unroll
                             for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = mfma(a, gw[p][ks][cb], acc[p][cb]);
                         } else {
-                            const T up = lam_mine[(0 * LC + p + 2 * i16) * LDP + 4 * ks + kk];
-                            const T um = lam_mine[(1 * LC + p + 2 * i16) * LDP + 4 * ks + kk];
+                            const T up = lam_w[(0 * LC + p * (LC / 2) + i16) * LDP + 4 * ks + kk];
+                            const T um = lam_w[(1 * LC + p * (LC / 2) + i16) * LDP + 4 * ks + kk];
                             const T aw = up + um, ax = up - um;
 #pragma unroll
                             for (int cb = 0; cb < NCB; ++cb) {
@@ -727,8 +716,8 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                         }
                     }
                 }
+                wave_sync();   // lambda reads issued: the region now takes the partial sums
             }
-            __syncthreads();   // lambda no longer needed: its LDS holds the partials
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -740,7 +729,7 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                         const int tl = col / CPJ, o = col % CPJ;
                         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                         const int e = (((tl * NCOMP + comp) * LC) + p + 2 * row) * 2 + reim;
-                        part[wave * NOUT + e] = active ? (double)acc[p][cb][r] : 0.0;
+                        part_w[e] = active ? (double)acc[p][cb][r] : 0.0;
                     }
             __syncthreads();
 #pragma unroll
@@ -750,8 +739,7 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                 if (e >= NOUT || l < l0 || l > lmax) continue;
                 double s = 0.0;
 #pragma unroll
-                for (int w = 0; w < LEG_NW; ++w) s += part[w * NOUT + e];
-                s *= SPIN ? 0.5 * fls[oloff[j]] : fls[oloff[j]];
+                for (int w = 0; w < LEG_NW; ++w) s += smem[w * REG_D + e];
                 if (grad && m > 0) s *= 2.0;   // fac_m of the real-field gradient
                 if (m == 0 && oreim[j]) s = 0.0;
                 obase[j][2 * (int64_t)l] = first ? s : pold[j] + s;
@@ -764,26 +752,30 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
 
 // ---------------------------------------------------------------- launchers
 
-// column blocks (16 columns each) per work group: bounded so that the
-// accumulators (synthesis) or the stationary phases (analysis) stay in
-// registers at two wavefronts per SIMD
-static int ncb_for(int spin, int ntrans, bool f32, bool anal)
+// column blocks (16 columns each) per analysis work group: bounded so that
+// the stationary phases stay in registers at two wavefronts per SIMD
+static int ncb_anal(int spin, int ntrans)
 {
     const int cols = ntrans * (spin ? 4 : 2);
     int ncb = (cols + 15) / 16;
-    (void)f32;
-    (void)anal;
     return ncb > 2 ? 2 : ncb;
+}
+
+// default column blocks per synthesis wavefront (the autotuner may change it)
+int synth_ncb_default(int spin, int ntrans, int precision)
+{
+    (void)precision;
+    if (spin == 0) return 1;      // 64-slot tiles: two column blocks would need 1 wavefront/SIMD
+    const int cols = ntrans * 4;
+    return cols > 16 ? 2 : 1;
 }
 
 template <int SPIN, int NCB, bool F32>
 static void launch_synth_t(const Plan &p, const LegView &v, const double *alm, double *phase,
                            hipStream_t s)
 {
-    const int jpg = NCB * 16 / (SPIN ? 4 : 2);
-    dim3 grid((unsigned)p.synth_items.size(), (unsigned)((p.ntrans + jpg - 1) / jpg));
-    hipLaunchKernelGGL((k_legendre_synth<SPIN, NCB, F32>), grid, dim3(64 * LEG_NW), 0, s, v,
-                       p.d_synth_items, alm, phase, jpg, p.flush_chunks);
+    hipLaunchKernelGGL((k_legendre_synth<SPIN, NCB, F32>), dim3((unsigned)p.synth_items.size()), dim3(64),
+                       0, s, v, p.d_synth_items, alm, phase, p.flush_chunks);
 }
 
 template <int SPIN, int NCB, bool F32>
@@ -797,24 +789,27 @@ static void launch_anal_t(const Plan &p, const LegView &v, const double *phase, 
 }
 
 template <bool F32>
-static void dispatch_synth(const Plan &p, const LegView &v, const double *alm, double *phase,
-                           hipStream_t s)
+static int dispatch_synth(const Plan &p, const LegView &v, const double *alm, double *phase,
+                          hipStream_t s)
 {
-    const int ncb = ncb_for(p.spin, p.ntrans, F32, false);
+    const int ncb = p.synth_ncb;
     if (p.spin == 0) {
         if (ncb == 1) launch_synth_t<0, 1, F32>(p, v, alm, phase, s);
-        else launch_synth_t<0, 2, F32>(p, v, alm, phase, s);
+        else if (ncb == 2) launch_synth_t<0, 2, F32>(p, v, alm, phase, s);
+        else return SHT_EINVAL;
     } else {
         if (ncb == 1) launch_synth_t<2, 1, F32>(p, v, alm, phase, s);
-        else launch_synth_t<2, 2, F32>(p, v, alm, phase, s);
+        else if (ncb == 2) launch_synth_t<2, 2, F32>(p, v, alm, phase, s);
+        else return SHT_EINVAL;
     }
+    return SHT_OK;
 }
 
 template <bool F32>
 static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, double *alm,
                           int grad, hipStream_t s)
 {
-    const int ncb = ncb_for(p.spin, p.ntrans, F32, true);
+    const int ncb = ncb_anal(p.spin, p.ntrans);
     if (p.spin == 0) {
         if (ncb == 1) launch_anal_t<0, 1, F32>(p, v, phase, alm, grad, s);
         else launch_anal_t<0, 2, F32>(p, v, phase, alm, grad, s);
@@ -828,8 +823,12 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipSt
 {
     if (p.synth_items.empty()) return SHT_OK;
     const LegView v = make_leg_view(p);
-    if (p.precision == SHT_FP32_MFMA) dispatch_synth<true>(p, v, alm, phase, s);
-    else dispatch_synth<false>(p, v, alm, phase, s);
+    const int rc = p.precision == SHT_FP32_MFMA ? dispatch_synth<true>(p, v, alm, phase, s)
+                                                : dispatch_synth<false>(p, v, alm, phase, s);
+    if (rc) {
+        set_error("synthesis column blocks %d not available", p.synth_ncb);
+        return rc;
+    }
     return check_hip(hipGetLastError(), "legendre synthesis launch");
 }
 

@@ -532,6 +532,53 @@ static void count_work(Plan &p)
     p.hbm_bytes = alm_b + 2.0 * ph_b + map_b;
 }
 
+// Synthesis work items (one wavefront each): (m, active slot tile, transform
+// group).  Blocks of four consecutive m go to one accelerator die (work group
+// i runs on die i mod NUM_XCD), so that the a_lm of an m and the cache lines
+// of its phases stay in one L2; blocks are dealt to the dies greedily by
+// cost, and each die's list runs from the longest degree range down.
+int build_synth_items(Plan &p)
+{
+    const int cpj = p.spin ? 4 : 2;
+    const int jpg = p.synth_ncb * 16 / cpj;
+    const int ngroups = (p.ntrans + jpg - 1) / jpg;
+    constexpr int MB = 4;
+    std::vector<std::vector<WaveItem>> die(NUM_XCD);
+    std::vector<double> load(NUM_XCD, 0.0);
+    for (int mb = 0; mb <= p.mmax; mb += MB) {
+        std::vector<WaveItem> blk;
+        double cost = 0.0;
+        for (int m = mb; m < std::min(p.mmax + 1, mb + MB); ++m) {
+            const double lrange = (double)(p.lmax + 1 - std::max(m, p.spin));
+            for (int t = 0; t < p.ntiles; ++t) {
+                if (p.tile_mlim[t] < m) continue;
+                for (int gI = 0; gI < ngroups; ++gI) {
+                    blk.push_back(WaveItem{m, t, gI * jpg, 0});
+                    cost += lrange;
+                }
+            }
+        }
+        if (blk.empty()) continue;
+        const int d = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[d] += cost;
+        die[d].insert(die[d].end(), blk.begin(), blk.end());
+    }
+    size_t longest = 0;
+    for (auto &l : die) longest = std::max(longest, l.size());
+    p.synth_items.assign(longest * NUM_XCD, WaveItem{-1, 0, 0, 0});
+    for (int d = 0; d < NUM_XCD; ++d)
+        for (size_t i = 0; i < die[d].size(); ++i) p.synth_items[i * NUM_XCD + d] = die[d][i];
+    p.n_items = (int64_t)p.synth_items.size();
+    dev_free(p.d_synth_items);
+    p.d_synth_items = nullptr;
+    if (p.synth_items.empty()) return SHT_OK;
+    int rc;
+    if ((rc = dev_alloc((void **)&p.d_synth_items, p.synth_items.size() * sizeof(WaveItem), "item list")))
+        return rc;
+    return dev_upload(p.d_synth_items, p.synth_items.data(), p.synth_items.size() * sizeof(WaveItem),
+                      "upload");
+}
+
 static int plan_build(Plan &p)
 {
     int rc;
@@ -584,30 +631,8 @@ static int plan_build(Plan &p)
     if ((rc = dev_alloc((void **)&p.d_tile_mlim, p.ntiles * sizeof(int), "tile table"))) return rc;
     if ((rc = dev_upload(p.d_tile_mlim, p.tile_mlim.data(), p.ntiles * sizeof(int), "upload"))) return rc;
 
-    // synthesis work items: m and up to LEG_NW active tiles, larger l-ranges first
-    p.synth_items.clear();
-    for (int m = 0; m <= p.mmax; ++m) {
-        LegItem it;
-        it.m = m;
-        int n = 0;
-        for (int t = 0; t < p.ntiles; ++t) {
-            if (p.tile_mlim[t] < m) continue;
-            it.tile[n++] = t;
-            if (n == LEG_NW) {
-                p.synth_items.push_back(it);
-                n = 0;
-            }
-        }
-        if (n) {
-            for (int k = n; k < LEG_NW; ++k) it.tile[k] = -1;
-            p.synth_items.push_back(it);
-        }
-    }
-    p.n_items = (int64_t)p.synth_items.size();
-    if (!p.synth_items.empty()) {
-        if ((rc = dev_alloc((void **)&p.d_synth_items, p.synth_items.size() * sizeof(LegItem), "item list"))) return rc;
-        if ((rc = dev_upload(p.d_synth_items, p.synth_items.data(), p.synth_items.size() * sizeof(LegItem), "upload"))) return rc;
-    }
+    p.synth_ncb = synth_ncb_default(p.spin, p.ntrans, p.precision);
+    if ((rc = build_synth_items(p))) return rc;
     p.anal_ms.resize(p.mmax + 1);
     for (int m = 0; m <= p.mmax; ++m) p.anal_ms[m] = m;
     if ((rc = dev_alloc((void **)&p.d_anal_ms, p.anal_ms.size() * sizeof(int), "m list"))) return rc;

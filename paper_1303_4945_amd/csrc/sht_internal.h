@@ -37,12 +37,16 @@ struct SlotHost {
     double chalf = 0, shalf = 0;  // cos t/2, sin t/2
 };
 
-constexpr int LEG_NW = 4;       // wavefronts per Legendre work group
+constexpr int LEG_NW = 4;       // wavefronts per analysis work group
+constexpr int NUM_XCD = 8;      // accelerator dies of the MI355X (work groups go round robin)
 
-// Synthesis work item: one m and up to LEG_NW slot tiles (-1: none).
-struct LegItem {
+// Synthesis work item of one wavefront: one m, one slot tile, one group of
+// transforms starting at t0 (m < 0: padding, no work).
+struct WaveItem {
     int m;
-    int tile[LEG_NW];
+    int tile;
+    int t0;
+    int pad;
 };
 
 // Per-(m, chain) start value: lambda_{l0} = sign * K * cos(t/2)^p * sin(t/2)^q.
@@ -99,7 +103,8 @@ struct Plan {
     int nslots = 0, ntiles = 0, slots_per_tile = 32;
     std::vector<int> tile_mlim;
     // host-side work lists
-    std::vector<LegItem> synth_items;
+    std::vector<WaveItem> synth_items;
+    int synth_ncb = 1;               // column blocks (16 columns) per synthesis item
     std::vector<int> anal_ms;
     // device memory
     double *d_slot_cos = nullptr, *d_slot_sin = nullptr, *d_slot_chalf = nullptr,
@@ -110,7 +115,7 @@ struct Plan {
     int64_t *d_coef_ofs = nullptr;
     StartCoef *d_start = nullptr;
     int *d_tile_mlim = nullptr;
-    LegItem *d_synth_items = nullptr;
+    WaveItem *d_synth_items = nullptr;
     int *d_anal_ms = nullptr;
     double *d_phase = nullptr;       // F / G workspace
     int64_t phase_elems = 0;         // complex elements
@@ -130,6 +135,8 @@ LegView make_leg_view(const Plan &p);
 
 // Legendre step launchers (legendre.hip)
 int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipStream_t s);
+int synth_ncb_default(int spin, int ntrans, int precision);
+int build_synth_items(Plan &p);
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, bool grad, hipStream_t s);
 
 // ring FFT (ringfft.hip)
