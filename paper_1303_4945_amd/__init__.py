@@ -262,3 +262,47 @@ class Plan:
         if h:
             _lib.sht_plan_destroy(h)
             self._h = None
+
+
+class Batch:
+    """Several plans (same spin and precision) executed as one unit: one
+    persistent Legendre launch over all plans plus every plan's ring FFTs; on a
+    non-default stream the launches are captured once into a HIP graph per
+    direction (re-captured when the buffers change) and replayed."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (_vp * len(self.plans))(*[p._h for p in self.plans])
+        h = _vp()
+        _check(_lib.sht_batch_create(len(self.plans), arr, ctypes.byref(h)))
+        self._h = h
+
+    def execute(self, direction, ins, outs=None, stream=None):
+        import torch
+        n = len(self.plans)
+        if len(ins) != n:
+            raise ValueError("one input per plan")
+        ins = [x.contiguous() for x in ins]
+        for x in ins:
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
+                raise TypeError("expected float64 CUDA tensors")
+        if outs is None:
+            shape = (lambda p: p.map_shape) if direction == ALM2MAP else (lambda p: p.alm_shape)
+            outs = [torch.empty(shape(p), dtype=torch.float64, device=x.device)
+                    for p, x in zip(self.plans, ins)]
+        a_in = (_vp * n)(*[x.data_ptr() for x in ins])
+        a_out = (_vp * n)(*[y.data_ptr() for y in outs])
+        _check(_lib.sht_batch_execute(self._h, direction, a_in, a_out, _stream_handle(stream)))
+        return outs
+
+    def alm2map(self, alms, outs=None, stream=None):
+        return self.execute(ALM2MAP, alms, outs, stream)
+
+    def map2alm(self, maps, outs=None, stream=None):
+        return self.execute(MAP2ALM, maps, outs, stream)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.sht_batch_destroy(h)
+            self._h = None

@@ -286,10 +286,16 @@ __device__ __forceinline__ double quad_rev(double x)
 // the X form by a lane exchange inside groups of four.  Class 0 collects the
 // terms whose mirror-ring sign is +1 (W at l + m even, X at l + m odd), class
 // 1 the others; ring t gets A0 + A1, ring pi - t gets A0 - A1.
+template <int SPIN, bool F32>
+struct SynShared {
+    typename MT<F32>::T lam[SYN_LC][SYN_ROW];
+    double4 cfs[2][SPIN ? 2 : 1][SYN_LC];
+};
+
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem *__restrict__ items,
-                                                       const double *__restrict__ alm,
-                                                       double *__restrict__ phase, int flush_chunks)
+__device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
+                                           const double *__restrict__ alm, double *__restrict__ phase,
+                                           int flush_chunks, SynShared<SPIN, F32> &sh)
 {
     using T = typename MT<F32>::T;
     using V = typename MT<F32>::V;
@@ -299,12 +305,11 @@ __global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem
     constexpr int LC = SYN_LC;
     constexpr int NCOMP = SPIN ? 2 : 1;
     constexpr int CPJ = SPIN ? 4 : 2;            // columns per transform
-    __shared__ T lam[LC][SYN_ROW];
-    __shared__ double4 cfs[2][NCH][LC];
+    auto &lam = sh.lam;
+    auto &cfs = sh.cfs;
 
     const int lane = threadIdx.x;
     const int i16 = lane & 15, kk = lane >> 4;
-    const WaveItem it = items[blockIdx.x];
     if (it.m < 0) return;
     const int m = it.m, tile = it.tile, t0 = it.t0;
     const int lmax = v.lmax;
@@ -348,18 +353,20 @@ __global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem
                 for (int cb = 0; cb < NCB; ++cb) {
                     const int l = lc + 8 * h + 2 * kk + par;
                     const bool ok = bok[cb] && l >= l0 && l <= lmax;
-                    dst[par][h][cb] = ok ? bp[cb][2 * (int64_t)l] : 0.0;
+                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);   // clamped address
+                    const double x = bp[cb][2 * (int64_t)lcl];
+                    dst[par][h][cb] = ok ? x : 0.0;
                 }
     };
     double4 qn = double4{0, 0, 0, 0};
     auto loadC = [&](int lc) {
-        if (lane < NCH * LC) {
-            const int t = lane % LC;
-            const int l = lc + t;
-            const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
-            const double f = (l >= l0 && l <= lmax) ? flm[l] * fscale : 0.0;
-            qn = chain_coef(c, lane >= LC, f);
-        }
+        const int l = lc + lane % LC;
+        const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);   // clamped address
+        const double4 c0 = coef[lcl];
+        const double f0 = flm[lcl];
+        const double4 c = (l >= l0 && l < lmax) ? c0 : double4{0, 0, 0, 0};
+        const double f = (l >= l0 && l <= lmax) ? f0 * fscale : 0.0;
+        qn = chain_coef(c, lane >= LC, f);
     };
     auto storeC = [&](int buf) {
         if (lane < NCH * LC) cfs[buf][lane / LC][lane % LC] = qn;
@@ -508,6 +515,36 @@ __global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem
             }
 }
 
+template <int SPIN, int NCB, bool F32>
+__global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem *__restrict__ items,
+                                                       const double *__restrict__ alm,
+                                                       double *__restrict__ phase, int flush_chunks)
+{
+    __shared__ SynShared<SPIN, F32> sh;
+    synth_item<SPIN, NCB, F32>(v, items[blockIdx.x], alm, phase, flush_chunks, sh);
+}
+
+// Persistent form for a batch of plans: every wavefront takes items from one
+// queue (ordered by cost) with an atomic counter until the queue is empty.
+template <int SPIN, int NCB, bool F32>
+__global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__restrict__ views,
+                                                             const BatchSynItem *__restrict__ items,
+                                                             int nitems, BatchPtrs ptrs, int flush_chunks,
+                                                             unsigned *counter)
+{
+    __shared__ SynShared<SPIN, F32> sh;
+    for (;;) {
+        unsigned idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(counter, 1u);
+        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0));
+        if (idx >= (unsigned)nitems) break;
+        const BatchSynItem bi = items[idx];
+        synth_item<SPIN, NCB, F32>(views[bi.plan], bi.it, ptrs.in[bi.plan], ptrs.out[bi.plan], flush_chunks,
+                                   sh);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- analysis
 
 constexpr int ANA_LC = 32;   // degrees per chunk (16 per parity class)
@@ -530,11 +567,26 @@ __device__ __forceinline__ void wave_sync()
 // tiles, and leaves its partial sums in the same region; after one work-group
 // barrier the partial sums of the wavefronts are added in a fixed order and
 // accumulated into a_lm (deterministic, no atomics).
+template <int SPIN, bool F32>
+struct AnaShape {
+    static constexpr int SPT = SPIN ? 32 : 64;
+    static constexpr int NCH = SPIN ? 2 : 1;
+    static constexpr int LDP = SPT + 1;
+    static constexpr int LAMW = NCH * ANA_LC * LDP;
+};
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
-                                                                  const double *__restrict__ phase,
-                                                                  double *__restrict__ alm,
-                                                                  int jobs_per_group, int grad)
+struct AnaShared {
+    static constexpr int LAMB = AnaShape<SPIN, F32>::LAMW * (int)sizeof(typename MT<F32>::T);
+    static constexpr int NOUTB = ANA_LC * NCB * 16 * 8;
+    static constexpr int REG_D = ((LAMB > NOUTB ? LAMB : NOUTB) + 7) / 8;
+    double smem[LEG_NW * REG_D];
+    double4 cfs[LEG_NW][SPIN ? 2 : 1][ANA_LC];
+};
+
+template <int SPIN, int NCB, bool F32>
+__device__ __forceinline__ void anal_item(const LegView &v, const int m, const int t0,
+                                          const double *__restrict__ phase, double *__restrict__ alm,
+                                          int grad, AnaShared<SPIN, NCB, F32> &sh)
 {
     using T = typename MT<F32>::T;
     using V = typename MT<F32>::V;
@@ -552,16 +604,13 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
     constexpr int LAMW = NCH * LC * LDP;   // lambda elements per wavefront
     // per wavefront: lambda [chain][row][LDP] (rows: even degree offsets, then
     // odd ones), reused for the wavefront's partial sums once its products are done
-    constexpr int REG_B = LAMW * (int)sizeof(T) > NOUT * 8 ? LAMW * (int)sizeof(T) : NOUT * 8;
-    constexpr int REG_D = (REG_B + 7) / 8;
-    __shared__ double smem[LEG_NW * REG_D];
-    __shared__ double4 cfs[LEG_NW][NCH][LC];
+    constexpr int REG_D = AnaShared<SPIN, NCB, F32>::REG_D;
+    double *smem = sh.smem;
+    auto &cfs = sh.cfs;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int i16 = lane & 15, kk = lane >> 4;
-    const int m = mlist[blockIdx.x];
-    const int t0 = blockIdx.y * jobs_per_group;
     const int lmax = v.lmax;
     const int l0 = m > SPIN ? m : SPIN;
     const int lstart = l0 - ((l0 + m) & 1);
@@ -622,15 +671,21 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
         // gw[q] multiplies W (spin 2) or lambda (spin 0) rows, gx[q] the X rows;
         // q = 0: G_t + G_(pi-t), q = 1: G_t - G_(pi-t).  For output o the X part
         // is sigma_o times the W operand of column 3 - o, sigma = (-, +, +, -).
+        // (all loads unconditional from clamped addresses, so that they are
+        // issued together rather than one conditional block at a time)
         T gw[2][KSA][NCB], gx[SPIN ? 2 : 1][SPIN ? KSA : 1][SPIN ? NCB : 1];
+        int ynv[KSA], ysv[KSA];
 #pragma unroll
         for (int ks = 0; ks < KSA; ++ks) {
-            const int slot = slot0 + 4 * ks + kk;
-            int yn = -1, ys = -1;
-            if (active && slot < v.nslots) {
-                yn = v.slot_yn[slot];
-                ys = v.slot_ys[slot];
-            }
+            const int slot = slot0 + 4 * ks + kk;     // < ntiles * SPT (tables padded)
+            const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
+            const bool ok = active && slot < v.nslots;
+            ynv[ks] = ok ? yn : -1;
+            ysv[ks] = ok ? ys : -1;
+        }
+#pragma unroll
+        for (int ks = 0; ks < KSA; ++ks) {
+            const int yn = ynv[ks], ys = ysv[ks];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
                 const int col = i16 + 16 * cb;
@@ -638,12 +693,12 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                 const int t = t0 + tl;
                 auto gval = [&](int oo, double &gsum, double &gdif) {
                     const int comp = SPIN ? (oo >> 1) : 0, reim = oo & 1;
-                    double gn = 0.0, gs = 0.0;
-                    if (t < v.ntrans) {
-                        const int64_t rowbase = ((int64_t)t * NCOMP + comp) * v.nrings;
-                        if (yn >= 0) gn = phase[((rowbase + yn) * (v.mmax + 1) + m) * 2 + reim];
-                        if (ys >= 0) gs = phase[((rowbase + ys) * (v.mmax + 1) + m) * 2 + reim];
-                    }
+                    const bool tok = t < v.ntrans;
+                    const int64_t rowbase = ((int64_t)(tok ? t : 0) * NCOMP + comp) * v.nrings;
+                    const double gn0 = phase[((rowbase + (yn >= 0 ? yn : 0)) * (v.mmax + 1) + m) * 2 + reim];
+                    const double gs0 = phase[((rowbase + (ys >= 0 ? ys : 0)) * (v.mmax + 1) + m) * 2 + reim];
+                    const double gn = (tok && yn >= 0) ? gn0 : 0.0;
+                    const double gs = (tok && ys >= 0) ? gs0 : 0.0;
                     gsum = gn + gs;
                     gdif = gn - gs;
                 };
@@ -665,13 +720,27 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
         const bool diff = wave_any(cs.x > DIFF_FORM_COS);
         if (diff) cs.aux = cs.mu;
         bool slow = wave_any(cs.k < 0);
+        // step coefficients of this lane's (chain, degree) entry, one chunk ahead
+        double4 qn = double4{0, 0, 0, 0};
+        auto loadC = [&](int lc) {
+            const int l = lc + (lane % LC);
+            const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);   // clamped address
+            const double4 c0 = coef[lcl];
+            const double f0 = flm[lcl];
+            const double4 c = (l >= l0 && l < lmax) ? c0 : double4{0, 0, 0, 0};
+            const double f = (l >= l0 && l <= lmax) ? f0 * (SPIN ? 0.5 : 1.0) : 0.0;
+            qn = chain_coef(c, lane >= LC, f);
+        };
+        loadC(lstart);
         for (int lc = lstart; lc <= lmax; lc += LC) {
             double pold[OPT];
             if (!first) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
                     const int l = lc + oloff[j];
-                    pold[j] = (l >= l0 && l <= lmax) ? obase[j][2 * (int64_t)l] : 0.0;
+                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+                    const double x = obase[j][2 * (int64_t)lcl];
+                    pold[j] = (l >= l0 && l <= lmax) ? x : 0.0;
                 }
             }
             V acc[2][NCB];   // [class][column block]
@@ -680,12 +749,8 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = V{0, 0, 0, 0};
             if (active) {
-                if (lane < NCH * LC) {
-                    const int l = lc + (lane % LC);
-                    const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
-                    const double f = (l >= l0 && l <= lmax) ? flm[l] * (SPIN ? 0.5 : 1.0) : 0.0;
-                    cfs[wave][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
-                }
+                if (lane < NCH * LC) cfs[wave][lane / LC][lane % LC] = qn;
+                if (lc + LC <= lmax) loadC(lc + LC);
                 wave_sync();
                 if (!slow && lc >= l0 && lc + LC <= lmax) {
                     chain_chunk_fast<T, LC, true>(cs, cfs[wave][rchain], diff, lam_out, LDP);
@@ -750,11 +815,47 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
     }
 }
 
+template <int SPIN, int NCB, bool F32>
+__global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
+                                                                  const double *__restrict__ phase,
+                                                                  double *__restrict__ alm,
+                                                                  int jobs_per_group, int grad)
+{
+    __shared__ AnaShared<SPIN, NCB, F32> sh;
+    anal_item<SPIN, NCB, F32>(v, mlist[blockIdx.x], (int)blockIdx.y * jobs_per_group, phase, alm, grad, sh);
+}
+
+// Persistent form for a batch of plans (one queue, atomic counter).
+template <int SPIN, int NCB, bool F32>
+__global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal_batch(const LegView *__restrict__ views,
+                                                                        const BatchAnaItem *__restrict__ items,
+                                                                        int nitems, BatchPtrs ptrs, int grad,
+                                                                        unsigned *counter)
+{
+    __shared__ AnaShared<SPIN, NCB, F32> sh;
+    __shared__ unsigned sidx;
+    for (;;) {
+        if (threadIdx.x == 0) sidx = atomicAdd(counter, 1u);
+        __syncthreads();
+        const unsigned idx = __builtin_amdgcn_readfirstlane(sidx);
+        __syncthreads();
+        if (idx >= (unsigned)nitems) break;
+        const BatchAnaItem bi = items[idx];
+        anal_item<SPIN, NCB, F32>(views[bi.plan], bi.m, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], grad, sh);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_counter(unsigned *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
 // ---------------------------------------------------------------- launchers
 
 // column blocks (16 columns each) per analysis work group: bounded so that
 // the stationary phases stay in registers at two wavefronts per SIMD
-static int ncb_anal(int spin, int ntrans)
+int anal_ncb(int spin, int ntrans)
 {
     const int cols = ntrans * (spin ? 4 : 2);
     int ncb = (cols + 15) / 16;
@@ -809,7 +910,7 @@ template <bool F32>
 static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, double *alm,
                           int grad, hipStream_t s)
 {
-    const int ncb = ncb_anal(p.spin, p.ntrans);
+    const int ncb = anal_ncb(p.spin, p.ntrans);
     if (p.spin == 0) {
         if (ncb == 1) launch_anal_t<0, 1, F32>(p, v, phase, alm, grad, s);
         else launch_anal_t<0, 2, F32>(p, v, phase, alm, grad, s);
@@ -838,6 +939,79 @@ int launch_legendre_anal(const Plan &p, const double *phase, double *alm, bool g
     if (p.precision == SHT_FP32_MFMA) dispatch_anal<true>(p, v, phase, alm, grad ? 1 : 0, s);
     else dispatch_anal<false>(p, v, phase, alm, grad ? 1 : 0, s);
     return check_hip(hipGetLastError(), "legendre analysis launch");
+}
+
+// ---------------------------------------------------------------- batches
+
+// work groups of a persistent launch: every CU filled to the kernel's occupancy
+template <typename K>
+static int persistent_groups(K kernel, int threads)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, threads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    const int g = ncu * (per_cu > 0 ? per_cu : 1);
+    return g > 0 ? g : 1024;
+}
+
+template <int SPIN, int NCB, bool F32>
+static void launch_synth_batch_t(const Batch &b, const BatchPtrs &ptrs, hipStream_t s)
+{
+    auto k = k_legendre_synth_batch<SPIN, NCB, F32>;
+    static const int groups = persistent_groups(k, 64);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
+    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64), 0, s, b.d_views, b.d_syn, b.nsyn, ptrs,
+                       b.plans[0]->flush_chunks, b.d_counter);
+}
+
+template <int SPIN, int NCB, bool F32>
+static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, bool grad, hipStream_t s)
+{
+    auto k = k_legendre_anal_batch<SPIN, NCB, F32>;
+    static const int groups = persistent_groups(k, 64 * LEG_NW);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
+    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * LEG_NW), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
+                       grad ? 1 : 0, b.d_counter);
+}
+
+int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, hipStream_t s)
+{
+    if (b.nsyn == 0) return SHT_OK;
+    const bool f32 = b.precision == SHT_FP32_MFMA;
+    const int key = (b.spin ? 4 : 0) + (b.syn_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
+    switch (key) {
+    case 0: launch_synth_batch_t<0, 1, false>(b, ptrs, s); break;
+    case 1: launch_synth_batch_t<0, 1, true>(b, ptrs, s); break;
+    case 2: launch_synth_batch_t<0, 2, false>(b, ptrs, s); break;
+    case 3: launch_synth_batch_t<0, 2, true>(b, ptrs, s); break;
+    case 4: launch_synth_batch_t<2, 1, false>(b, ptrs, s); break;
+    case 5: launch_synth_batch_t<2, 1, true>(b, ptrs, s); break;
+    case 6: launch_synth_batch_t<2, 2, false>(b, ptrs, s); break;
+    default: launch_synth_batch_t<2, 2, true>(b, ptrs, s); break;
+    }
+    return check_hip(hipGetLastError(), "batch legendre synthesis launch");
+}
+
+int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, bool grad, hipStream_t s)
+{
+    if (b.nana == 0) return SHT_OK;
+    const bool f32 = b.precision == SHT_FP32_MFMA;
+    const int key = (b.spin ? 4 : 0) + (b.ana_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
+    switch (key) {
+    case 0: launch_anal_batch_t<0, 1, false>(b, ptrs, grad, s); break;
+    case 1: launch_anal_batch_t<0, 1, true>(b, ptrs, grad, s); break;
+    case 2: launch_anal_batch_t<0, 2, false>(b, ptrs, grad, s); break;
+    case 3: launch_anal_batch_t<0, 2, true>(b, ptrs, grad, s); break;
+    case 4: launch_anal_batch_t<2, 1, false>(b, ptrs, grad, s); break;
+    case 5: launch_anal_batch_t<2, 1, true>(b, ptrs, grad, s); break;
+    case 6: launch_anal_batch_t<2, 2, false>(b, ptrs, grad, s); break;
+    default: launch_anal_batch_t<2, 2, true>(b, ptrs, grad, s); break;
+    }
+    return check_hip(hipGetLastError(), "batch legendre analysis launch");
 }
 
 }  // namespace sht

@@ -1006,6 +1006,8 @@ static int mode_of(const FftLen &d)
     return KMODE_LDS;
 }
 
+static int prepare_groups(const FftDev &D);
+
 int fft_plan_build(Plan &p)
 {
     const Geom &g = p.geom;
@@ -1125,6 +1127,7 @@ int fft_plan_build(Plan &p)
     p.fft.d_rows = D;
     p.fft.nrows = (int)H.rows.size();
     p.fft.table_bytes = H.ctab.size() * sizeof(double2) + H.itab.size() * sizeof(int);
+    if ((rc = prepare_groups(*D))) return rc;
     // Bluestein kernel spectra on the device
     FftView v = view_of(p, *D);
     for (int li = 0; li < (int)H.lens.size(); ++li) {
@@ -1176,17 +1179,41 @@ void fft_plan_free(FftPlan &f)
     f.d_rows = nullptr;
 }
 
+// Allows the group's kernels their dynamic LDS size (once, at plan time, so that
+// launches stay pure stream work and can be captured in a graph).
+template <int MODE, bool POW2>
+static int prepare_group(const FftGroup &gr)
+{
+    const size_t lds = (size_t)lds_padded(gr.lds_complex) * sizeof(double2);
+    if (lds <= 65536) return SHT_OK;
+    int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_synth<MODE, POW2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                       "fft LDS attribute");
+    if (rc) return rc;
+    return check_hip(hipFuncSetAttribute((const void *)k_ring_anal<MODE, POW2>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                     "fft LDS attribute");
+}
+
+static int prepare_groups(const FftDev &D)
+{
+    for (const FftGroup &gr : D.groups) {
+        int rc;
+        if (gr.mode == KMODE_SPLIT) rc = prepare_group<KMODE_SPLIT, true>(gr);
+        else if (gr.mode == KMODE_RADER && gr.pow2) rc = prepare_group<KMODE_RADER, true>(gr);
+        else if (gr.mode == KMODE_RADER) rc = prepare_group<KMODE_RADER, false>(gr);
+        else if (gr.pow2) rc = prepare_group<KMODE_LDS, true>(gr);
+        else rc = prepare_group<KMODE_LDS, false>(gr);
+        if (rc) return rc;
+    }
+    return SHT_OK;
+}
+
 template <int MODE, bool POW2>
 static int launch_group_synth(const FftView &v, const FftGroup &gr, const int *rows,
                               const double *phase, double *map, int ntc, hipStream_t s)
 {
     const size_t lds = (size_t)lds_padded(gr.lds_complex) * sizeof(double2);
-    if (lds > 65536) {
-        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_synth<MODE, POW2>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                           "fft LDS attribute");
-        if (rc) return rc;
-    }
     hipLaunchKernelGGL((k_ring_synth<MODE, POW2>), dim3((unsigned)gr.rows.size(), (unsigned)ntc),
                        dim3(threads_for(gr)), lds, s, v, rows, phase, map);
     return SHT_OK;
@@ -1197,12 +1224,6 @@ static int launch_group_anal(const FftView &v, const FftGroup &gr, const int *ro
                              double *phase, int ntc, int usew, hipStream_t s)
 {
     const size_t lds = (size_t)lds_padded(gr.lds_complex) * sizeof(double2);
-    if (lds > 65536) {
-        int rc = check_hip(hipFuncSetAttribute((const void *)k_ring_anal<MODE, POW2>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                           "fft LDS attribute");
-        if (rc) return rc;
-    }
     hipLaunchKernelGGL((k_ring_anal<MODE, POW2>), dim3((unsigned)gr.rows.size(), (unsigned)ntc),
                        dim3(threads_for(gr)), lds, s, v, rows, map, phase, usew);
     return SHT_OK;

@@ -676,6 +676,47 @@ static bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb)
     return a0 < b0 + nb && b0 < a0 + na;
 }
 
+int check_exec_args(const Plan *p, int direction, const void *in, const void *out, bool stage_fft,
+                    bool stage_leg)
+{
+    if (direction != SHT_ALM2MAP && direction != SHT_MAP2ALM && direction != SHT_ALM2MAP_ADJOINT &&
+        direction != SHT_ALM2MAP_GRAD) {
+        set_error("unknown direction %d", direction);
+        return SHT_EINVAL;
+    }
+    if (!in || !out) { set_error("in and out must be device pointers"); return SHT_EINVAL; }
+    if (direction == SHT_MAP2ALM && !p->geom.has_weight && !stage_leg) {
+        set_error("geometry has no ring weights: analysis unavailable (use the adjoint)");
+        return SHT_EINVAL;
+    }
+    const size_t alm_b = (size_t)p->ntrans * p->ncomp * p->nalm * 16;
+    const size_t map_b = (size_t)p->ntrans * p->ncomp * p->geom.npix * 8;
+    const size_t ph_b = (size_t)p->phase_elems * 16;
+    size_t in_b, out_b;
+    if (direction == SHT_ALM2MAP) {
+        in_b = stage_fft ? ph_b : alm_b;
+        out_b = stage_leg ? ph_b : map_b;
+    } else {
+        in_b = stage_leg ? ph_b : map_b;
+        out_b = stage_fft ? ph_b : alm_b;
+    }
+    if (ranges_overlap(in, in_b, out, out_b)) { set_error("input and output buffers overlap"); return SHT_EINVAL; }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+        (void)hipGetLastError();
+        set_error("current device differs from the plan's device %d", p->device);
+        return SHT_EDEVICE;
+    }
+    return SHT_OK;
+}
+
+int finish_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return check_hip(e, what);
+    return SHT_OK;
+}
+
 }  // namespace sht
 
 extern "C" {
@@ -742,47 +783,6 @@ void sht_plan_destroy(sht_plan *h)
     plan_free_device(p);
     p->magic = kDeadMagic;
     delete p;
-}
-
-static int check_exec_args(Plan *p, int direction, const double *in, double *out, bool stage_fft,
-                           bool stage_leg)
-{
-    if (direction != SHT_ALM2MAP && direction != SHT_MAP2ALM && direction != SHT_ALM2MAP_ADJOINT &&
-        direction != SHT_ALM2MAP_GRAD) {
-        set_error("unknown direction %d", direction);
-        return SHT_EINVAL;
-    }
-    if (!in || !out) { set_error("in and out must be device pointers"); return SHT_EINVAL; }
-    if (direction == SHT_MAP2ALM && !p->geom.has_weight && !stage_leg) {
-        set_error("geometry has no ring weights: analysis unavailable (use the adjoint)");
-        return SHT_EINVAL;
-    }
-    const size_t alm_b = (size_t)p->ntrans * p->ncomp * p->nalm * 16;
-    const size_t map_b = (size_t)p->ntrans * p->ncomp * p->geom.npix * 8;
-    const size_t ph_b = (size_t)p->phase_elems * 16;
-    size_t in_b, out_b;
-    if (direction == SHT_ALM2MAP) {
-        in_b = stage_fft ? ph_b : alm_b;
-        out_b = stage_leg ? ph_b : map_b;
-    } else {
-        in_b = stage_leg ? ph_b : map_b;
-        out_b = stage_fft ? ph_b : alm_b;
-    }
-    if (ranges_overlap(in, in_b, out, out_b)) { set_error("input and output buffers overlap"); return SHT_EINVAL; }
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
-        (void)hipGetLastError();
-        set_error("current device differs from the plan's device %d", p->device);
-        return SHT_EDEVICE;
-    }
-    return SHT_OK;
-}
-
-static int finish_launch(const char *what)
-{
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return check_hip(e, what);
-    return SHT_OK;
 }
 
 int sht_execute(sht_plan *h, int direction, const double *in, double *out, void *hip_stream)

@@ -49,6 +49,18 @@ struct WaveItem {
     int pad;
 };
 
+// Items of the persistent batch kernels (plan index into the batch's tables).
+struct BatchSynItem {
+    int plan;
+    WaveItem it;
+};
+struct BatchAnaItem {
+    int plan;
+    int m;
+    int t0;
+    int pad;
+};
+
 // Per-(m, chain) start value: lambda_{l0} = sign * K * cos(t/2)^p * sin(t/2)^q.
 struct StartCoef {
     double kmant;   // mantissa of K in [0.5, 1)
@@ -126,9 +138,28 @@ struct Plan {
     int synth_waves = 1;
 };
 
+constexpr int MAX_BATCH_PLANS = 64;
+
+// Legendre-step operands of the plans of a batch, passed by value to the
+// persistent kernels (so that a captured graph holds them as parameters).
+struct BatchPtrs {
+    const double *in[MAX_BATCH_PLANS];
+    double *out[MAX_BATCH_PLANS];
+};
+
 struct Batch {
     uint32_t magic = kBatchMagic;
     std::vector<Plan *> plans;
+    int spin = 0, precision = 0, syn_ncb = 1, ana_ncb = 1;
+    int nsyn = 0, nana = 0;
+    LegView *d_views = nullptr;
+    BatchSynItem *d_syn = nullptr;
+    BatchAnaItem *d_ana = nullptr;
+    unsigned *d_counter = nullptr;
+    // captured graphs, one per direction, keyed by the user pointers
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<const void *> graph_key[4];
+    hipStream_t graph_stream[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 LegView make_leg_view(const Plan &p);
@@ -138,6 +169,11 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipSt
 int synth_ncb_default(int spin, int ntrans, int precision);
 int build_synth_items(Plan &p);
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, bool grad, hipStream_t s);
+
+// persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
+int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, hipStream_t s);
+int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, bool grad, hipStream_t s);
+int anal_ncb(int spin, int ntrans);
 
 // ring FFT (ringfft.hip)
 int fft_plan_build(Plan &p);
@@ -151,5 +187,8 @@ int dev_alloc(void **ptr, size_t bytes, const char *what);
 void dev_free(void *ptr);
 int dev_upload(void *dst, const void *src, size_t bytes, const char *what);
 int check_hip(hipError_t e, const char *what);
+int check_exec_args(const Plan *p, int direction, const void *in, const void *out, bool fft_only,
+                    bool leg_only);
+int finish_launch(const char *what);
 
 }  // namespace sht

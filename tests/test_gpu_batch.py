@@ -1,0 +1,164 @@
+"""Batches of plans (persistent Legendre kernels over a cost-ordered queue,
+HIP-graph replay) and the autotuner, on the GPU.
+
+A batch item runs the same per-item arithmetic as the plan's own launch, so
+batch results must equal the single-plan results bit for bit; one plan of
+each batch is also checked against the oracle (tolerance as in the parity
+tests)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import sht_inputs as si
+from gpu_util import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def _sht():
+    import paper_1303_4945_amd as sht
+    return sht
+
+
+def _mixed(lmaxes, ntrans, spin=0, precision="fp64"):
+    sht = _sht()
+    geoms, plans, alms = [], [], []
+    for k, lmax in enumerate(lmaxes):
+        g = si.gauss_geometry(lmax + 1, 2 * lmax + 1, 0.1 * k)
+        geoms.append(g)
+        plans.append(sht.Plan(sht.Geometry.from_inputs(g), lmax, spin=spin, ntrans=ntrans,
+                              precision=precision))
+        alms.append(si.random_alm(lmax, lmax, ntrans, spin, tag=100 + k))
+    return geoms, plans, alms
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_batch_equals_single_plans_and_oracle(spin):
+    sht = _sht()
+    lmaxes = [31, 63, 95] if spin == 0 else [23, 47]
+    geoms, plans, alms = _mixed(lmaxes, 3, spin)
+    b = sht.Batch(plans)
+    d_alm = [to_dev(a) for a in alms]
+    maps = b.alm2map(d_alm)
+    for p, a, mp in zip(plans, d_alm, maps):
+        assert np.array_equal(to_host(mp), to_host(p.alm2map(a))), "batch synthesis != plan synthesis"
+    back = b.map2alm(maps)
+    for p, mp, ab in zip(plans, maps, back):
+        assert np.array_equal(to_host(ab), to_host(p.map2alm(mp))), "batch analysis != plan analysis"
+    adj = b.execute(sht.ALM2MAP_ADJOINT, maps)
+    for p, mp, aj in zip(plans, maps, adj):
+        assert np.array_equal(to_host(aj), to_host(p.adjoint(mp)))
+    # oracle parity for the first plan
+    g, lmax = geoms[0], lmaxes[0]
+    ref_map = oracle.synthesis(g, lmax, lmax, spin, alms[0])
+    assert rel_err(to_host(maps[0]), ref_map) < TOL64
+    ref_alm = oracle.analysis(g, lmax, lmax, spin, to_host(maps[0]))
+    assert rel_err(to_host(back[0]), ref_alm) < TOL64
+
+
+def test_batch_graph_replays_match_eager():
+    """The captured graph is replayed several times with eager work and
+    synchronisations in between; every replay must equal the eager result."""
+    import torch
+    sht = _sht()
+    lmaxes = [31, 47, 63]
+    geoms, plans, alms = _mixed(lmaxes, 2, 0)
+    b = sht.Batch(plans)
+    d_alm = [to_dev(a) for a in alms]
+    eager = [to_host(p.alm2map(a)) for p, a in zip(plans, d_alm)]
+    eager_back = [to_host(p.map2alm(to_dev(e))) for p, e in zip(plans, eager)]
+    s = torch.cuda.Stream()
+    outs = [torch.empty(p.map_shape, dtype=torch.float64, device="cuda") for p in plans]
+    backs = [torch.empty(p.alm_shape, dtype=torch.float64, device="cuda") for p in plans]
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            b.alm2map(d_alm, outs, stream=s)
+            b.map2alm(outs, backs, stream=s)
+        s.synchronize()
+        for k in range(len(plans)):
+            assert np.array_equal(to_host(outs[k]), eager[k]), f"replay {rep}, plan {k}"
+            assert np.array_equal(to_host(backs[k]), eager_back[k]), f"replay {rep}, plan {k} analysis"
+        # eager work on the default stream between replays
+        _ = plans[0].alm2map(d_alm[0])
+        torch.cuda.synchronize()
+
+
+def test_batch_fp32_precision_form():
+    sht = _sht()
+    geoms, plans, alms = _mixed([31, 63], 4, 2, precision="fp32_mfma")
+    b = sht.Batch(plans)
+    d_alm = [to_dev(a) for a in alms]
+    maps = b.alm2map(d_alm)
+    for p, a, mp in zip(plans, d_alm, maps):
+        assert np.array_equal(to_host(mp), to_host(p.alm2map(a)))
+    ref = oracle.synthesis(geoms[1], 63, 63, 2, alms[1])
+    assert rel_err(to_host(maps[1]), ref) < 1e-6
+
+
+def test_batch_rejects_mixed_spin():
+    sht = _sht()
+    _, p0, _ = _mixed([15], 1, 0)
+    _, p2, _ = _mixed([15], 1, 2)
+    with pytest.raises(sht.ShtError):
+        sht.Batch([p0[0], p2[0]])
+
+
+def test_mixed_lmax_workload_batch():
+    """The mixed batch workload: GL grids for lmax 255/511/1023/2047 with 16
+    scalar transforms each, one persistent launch per direction; equal to the
+    single plans, and the lmax 255 plan checked against the oracle on sampled
+    rings and m values."""
+    import torch
+    sht = _sht()
+    lmaxes = [255, 511, 1023, 2047]
+    geoms, plans, alms = _mixed(lmaxes, 16, 0)
+    b = sht.Batch(plans)
+    d_alm = [to_dev(a) for a in alms]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        maps = b.alm2map(d_alm, stream=s)
+        back = b.map2alm(maps, stream=s)
+    s.synchronize()
+    for k, p in enumerate(plans):
+        assert np.array_equal(to_host(maps[k]), to_host(p.alm2map(d_alm[k])))
+        assert np.array_equal(to_host(back[k]), to_host(p.map2alm(maps[k])))
+    g, lmax = geoms[0], 255
+    rings = np.array([0, 1, 77, 128, 200, 255])
+    ref = oracle.synthesis(g, lmax, lmax, 0, alms[0][:2], rings=rings)
+    pix = np.concatenate([np.arange(g.ofs[y], g.ofs[y] + g.nphi[y]) for y in rings])
+    assert rel_err(to_host(maps[0])[:2][..., pix], ref[..., pix]) < TOL64
+    ms = np.array([0, 1, 2, 128, 254, 255])
+    ref_a = oracle.analysis(g, lmax, lmax, 0, to_host(maps[0])[:2], ms=ms)
+    sel = np.concatenate([np.arange(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+                          for m in ms])
+    assert rel_err(to_host(back[0])[:2][:, :, sel], ref_a[:, :, sel]) < TOL64
+    # GL quadrature is exact here: the round trip returns the input
+    assert rel_err(to_host(back[3]), alms[3]) < 1e-10
+
+
+def test_autotune_keeps_results_and_writes_cache(tmp_path):
+    sht = _sht()
+    os.environ["SHT_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        g = si.gauss_geometry(128, 255)
+        p = sht.Plan(sht.Geometry.from_inputs(g), 127, spin=2, ntrans=8)
+        a = to_dev(si.random_alm(127, 127, 8, 2, tag=5))
+        before = to_host(p.alm2map(a))
+        p.autotune(2.0)
+        after = to_host(p.alm2map(a))
+        assert np.array_equal(before, after)
+        text = (tmp_path / "tune.txt").read_text()
+        assert "lmax=127" in text and "spin=2" in text
+        # a second plan of the same shape takes the cached choice without timing
+        p2 = sht.Plan(sht.Geometry.from_inputs(g), 127, spin=2, ntrans=8)
+        p2.autotune(0.0)
+        assert np.array_equal(to_host(p2.alm2map(a)), before)
+    finally:
+        del os.environ["SHT_TUNE_CACHE"]
