@@ -329,20 +329,22 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
     if (diff) cs.aux = cs.mu;
     bool slow = wave_any(cs.k < 0);
 
-    // B operand sources: this lane's column in each column block
+    // B operand sources: this lane's column in each column block (columns that
+    // take no part -- beyond the last transform, or Im at m = 0 -- read zeros)
     const double *bp[NCB];
-    bool bok[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
         const int col = i16 + 16 * cb;
         const int t = t0 + col / CPJ, o = col % CPJ;
         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
-        bok[cb] = t < v.ntrans && !(m == 0 && reim);
-        bp[cb] = alm + (((int64_t)(bok[cb] ? t : 0) * NCOMP + comp) * v.nalm + mbase) * 2 + reim;
+        const bool ok = t < v.ntrans && !(m == 0 && reim);
+        bp[cb] = ok ? alm + (((int64_t)t * NCOMP + comp) * v.nalm + mbase) * 2 + reim : v.zeros;
     }
     const bool xneg = SPIN && ((i16 & 3) == 1 || (i16 & 3) == 2);
 
-    // raw coefficients of a chunk: R[par][h][cb] = a(column, lc + 8h + 2kk + par)
+    // coefficients of a chunk: R[par][h][cb] = a(column, lc + 8h + 2kk + par),
+    // loaded one chunk ahead from clamped addresses; degrees outside [l0, lmax]
+    // meet lambda = 0 in the products, so the values there need no masking
     double R[2][2][NCB], Rn[2][2][NCB];
     auto loadB = [&](int lc, double (&dst)[2][2][NCB]) {
 #pragma unroll
@@ -352,24 +354,23 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) {
                     const int l = lc + 8 * h + 2 * kk + par;
-                    const bool ok = bok[cb] && l >= l0 && l <= lmax;
-                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);   // clamped address
-                    const double x = bp[cb][2 * (int64_t)lcl];
-                    dst[par][h][cb] = ok ? x : 0.0;
+                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+                    dst[par][h][cb] = bp[cb][2 * (int64_t)lcl];
                 }
     };
-    double4 qn = double4{0, 0, 0, 0};
+    double4 c0n = double4{0, 0, 0, 0};
+    double f0n = 0.0;
     auto loadC = [&](int lc) {
         const int l = lc + lane % LC;
         const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);   // clamped address
-        const double4 c0 = coef[lcl];
-        const double f0 = flm[lcl];
-        const double4 c = (l >= l0 && l < lmax) ? c0 : double4{0, 0, 0, 0};
-        const double f = (l >= l0 && l <= lmax) ? f0 * fscale : 0.0;
-        qn = chain_coef(c, lane >= LC, f);
+        c0n = coef[lcl];
+        f0n = flm[lcl];
     };
-    auto storeC = [&](int buf) {
-        if (lane < NCH * LC) cfs[buf][lane / LC][lane % LC] = qn;
+    auto storeC = [&](int buf, int lc) {
+        const int l = lc + lane % LC;
+        const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
+        const double f = (l >= l0 && l <= lmax) ? f0n * fscale : 0.0;
+        if (lane < NCH * LC) cfs[buf][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
     };
 
     V acc[2][NSB][NCB];
@@ -393,7 +394,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
 
     loadB(lstart, R);
     loadC(lstart);
-    storeC(0);
+    storeC(0, lstart);
     __syncthreads();
     int chunk = 0;
     for (int lc = lstart; lc <= lmax; lc += LC, ++chunk) {
@@ -475,7 +476,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
             }
         }
         if (more) {
-            storeC(buf ^ 1);
+            storeC(buf ^ 1, lc + LC);
 #pragma unroll
             for (int par = 0; par < 2; ++par)
 #pragma unroll
@@ -485,6 +486,17 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         }
         __syncthreads();
     }
+
+    // ring indices of this lane's output rows, all loaded before any store
+    int eyn[NSB][4], eys[NSB][4];
+#pragma unroll
+    for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int slot = tile * SPT + sb * 16 + c_row<F32>(lane, r);   // < ntiles * SPT
+            eyn[sb][r] = v.slot_yn[slot];
+            eys[sb][r] = v.slot_ys[slot];
+        }
 
     // epilogue: ring t = A0 + A1, ring pi - t = A0 - A1
 #pragma unroll
@@ -508,7 +520,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
                 const int t = t0 + col / CPJ, o = col % CPJ;
                 if (t >= v.ntrans) continue;
                 const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
-                const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
+                const int yn = eyn[sb][r], ys = eys[sb][r];
                 const int64_t rowbase = ((int64_t)t * NCOMP + comp) * v.nrings;
                 if (yn >= 0) phase[((rowbase + yn) * (v.mmax + 1) + m) * 2 + reim] = c0 + c1;
                 if (ys >= 0) phase[((rowbase + ys) * (v.mmax + 1) + m) * 2 + reim] = c0 - c1;
@@ -668,12 +680,14 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
         const bool active = ptile >= 0;
         const int slot0 = active ? ptile * SPT : 0;
         // stationary phase fragments B[kk][j] for slot 4 ks + kk and column j + 16 cb:
-        // gw[q] multiplies W (spin 2) or lambda (spin 0) rows, gx[q] the X rows;
-        // q = 0: G_t + G_(pi-t), q = 1: G_t - G_(pi-t).  For output o the X part
-        // is sigma_o times the W operand of column 3 - o, sigma = (-, +, +, -).
+        // gw[q] multiplies W (spin 2) or lambda (spin 0) rows; q = 0: G_t + G_(pi-t),
+        // q = 1: G_t - G_(pi-t).  For output o the X rows take sigma_o times the W
+        // operand of column 3 - o, sigma = (-, +, +, -): formed when needed by a
+        // lane exchange within the four columns of a transform.
         // (all loads unconditional from clamped addresses, so that they are
         // issued together rather than one conditional block at a time)
-        T gw[2][KSA][NCB], gx[SPIN ? 2 : 1][SPIN ? KSA : 1][SPIN ? NCB : 1];
+        T gw[2][KSA][NCB];
+        const bool xneg = SPIN && ((i16 & 3) == 0 || (i16 & 3) == 3);
         int ynv[KSA], ysv[KSA];
 #pragma unroll
         for (int ks = 0; ks < KSA; ++ks) {
@@ -707,29 +721,21 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 const double sg = SPIN ? -1.0 : 1.0;
                 gw[0][ks][cb] = (T)(sg * a);
                 gw[1][ks][cb] = (T)(sg * b);
-                if constexpr (SPIN) {
-                    double c, d;
-                    gval(3 - o, c, d);
-                    const double sx = (o == 0 || o == 3) ? 1.0 : -1.0;   // sigma_o * (-1)
-                    gx[0][ks][cb] = (T)(sx * c);
-                    gx[1][ks][cb] = (T)(sx * d);
-                }
             }
         }
         Chain cs = chain_init(v, m, active ? ptile * SPT + rslot : v.nslots, rchain);
         const bool diff = wave_any(cs.x > DIFF_FORM_COS);
         if (diff) cs.aux = cs.mu;
         bool slow = wave_any(cs.k < 0);
-        // step coefficients of this lane's (chain, degree) entry, one chunk ahead
-        double4 qn = double4{0, 0, 0, 0};
+        // step coefficients of this lane's (chain, degree) entry, loaded one
+        // chunk ahead from a clamped address and masked when staged
+        double4 c0n = double4{0, 0, 0, 0};
+        double f0n = 0.0;
         auto loadC = [&](int lc) {
             const int l = lc + (lane % LC);
-            const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);   // clamped address
-            const double4 c0 = coef[lcl];
-            const double f0 = flm[lcl];
-            const double4 c = (l >= l0 && l < lmax) ? c0 : double4{0, 0, 0, 0};
-            const double f = (l >= l0 && l <= lmax) ? f0 * (SPIN ? 0.5 : 1.0) : 0.0;
-            qn = chain_coef(c, lane >= LC, f);
+            const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+            c0n = coef[lcl];
+            f0n = flm[lcl];
         };
         loadC(lstart);
         for (int lc = lstart; lc <= lmax; lc += LC) {
@@ -739,8 +745,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 for (int j = 0; j < OPT; ++j) {
                     const int l = lc + oloff[j];
                     const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
-                    const double x = obase[j][2 * (int64_t)lcl];
-                    pold[j] = (l >= l0 && l <= lmax) ? x : 0.0;
+                    pold[j] = obase[j][2 * (int64_t)lcl];   // used only where l is in range
                 }
             }
             V acc[2][NCB];   // [class][column block]
@@ -749,7 +754,12 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = V{0, 0, 0, 0};
             if (active) {
-                if (lane < NCH * LC) cfs[wave][lane / LC][lane % LC] = qn;
+                {
+                    const int l = lc + (lane % LC);
+                    const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
+                    const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) : 0.0;
+                    if (lane < NCH * LC) cfs[wave][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
+                }
                 if (lc + LC <= lmax) loadC(lc + LC);
                 wave_sync();
                 if (!slow && lc >= l0 && lc + LC <= lmax) {
@@ -776,7 +786,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
 #pragma unroll
                             for (int cb = 0; cb < NCB; ++cb) {
                                 acc[p][cb] = mfma(aw, gw[p][ks][cb], acc[p][cb]);
-                                acc[p][cb] = mfma(ax, gx[1 - p][ks][cb], acc[p][cb]);
+                                const T q = quad_rev(gw[1 - p][ks][cb]);
+                                acc[p][cb] = mfma(ax, xneg ? -q : q, acc[p][cb]);
                             }
                         }
                     }

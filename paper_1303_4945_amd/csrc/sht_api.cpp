@@ -313,12 +313,14 @@ static void plan_free_device(Plan *p)
     dev_free(p->d_slot_yn); dev_free(p->d_slot_ys);
     dev_free(p->d_coef); dev_free(p->d_fl); dev_free(p->d_coef_ofs); dev_free(p->d_start);
     dev_free(p->d_tile_mlim); dev_free(p->d_synth_items); dev_free(p->d_anal_ms);
+    dev_free(p->d_zeros);
     dev_free(p->d_phase);
     fft_plan_free(p->fft);
     p->d_slot_cos = p->d_slot_sin = p->d_slot_chalf = p->d_slot_shalf = nullptr;
     p->d_slot_yn = p->d_slot_ys = nullptr;
     p->d_coef = nullptr; p->d_fl = nullptr; p->d_coef_ofs = nullptr; p->d_start = nullptr;
     p->d_tile_mlim = nullptr; p->d_synth_items = nullptr; p->d_anal_ms = nullptr;
+    p->d_zeros = nullptr;
     p->d_phase = nullptr;
 }
 
@@ -631,6 +633,11 @@ static int plan_build(Plan &p)
     if ((rc = dev_alloc((void **)&p.d_tile_mlim, p.ntiles * sizeof(int), "tile table"))) return rc;
     if ((rc = dev_upload(p.d_tile_mlim, p.tile_mlim.data(), p.ntiles * sizeof(int), "upload"))) return rc;
 
+    {
+        const size_t zb = (size_t)2 * (p.lmax + 2) * sizeof(double);
+        if ((rc = dev_alloc((void **)&p.d_zeros, zb, "zero operands"))) return rc;
+        if ((rc = check_hip(hipMemset(p.d_zeros, 0, zb), "zero operands"))) return rc;
+    }
     p.synth_ncb = synth_ncb_default(p.spin, p.ntrans, p.precision);
     if ((rc = build_synth_items(p))) return rc;
     p.anal_ms.resize(p.mmax + 1);
@@ -659,6 +666,7 @@ LegView make_leg_view(const Plan &p)
     v.slot_yn = p.d_slot_yn; v.slot_ys = p.d_slot_ys;
     v.coef = p.d_coef; v.fl = p.d_fl; v.coef_ofs = p.d_coef_ofs; v.start = p.d_start;
     v.tile_mlim = p.d_tile_mlim;
+    v.zeros = p.d_zeros;
     v.nalm = p.nalm;
     return v;
 }

@@ -83,6 +83,7 @@ struct LegView {
     const int64_t *coef_ofs;    // coef + coef_ofs[m] + l  for l >= l0(m) (same for fl)
     const StartCoef *start;     // [m][chain] chain 0: +s (or 0), chain 1: -s
     const int *tile_mlim;       // per tile: largest m with an active slot (-1: none)
+    const double *zeros;        // 2 (lmax + 1) zeros: operand source of unused columns
     int64_t nalm;
 };
 
@@ -127,6 +128,7 @@ struct Plan {
     int64_t *d_coef_ofs = nullptr;
     StartCoef *d_start = nullptr;
     int *d_tile_mlim = nullptr;
+    double *d_zeros = nullptr;
     WaveItem *d_synth_items = nullptr;
     int *d_anal_ms = nullptr;
     double *d_phase = nullptr;       // F / G workspace
