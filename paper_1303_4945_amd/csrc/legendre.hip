@@ -152,8 +152,10 @@ __device__ inline double4 chain_coef(const double4 c, bool minus, double fs)
     return minus ? double4{c.x, -c.y, c.w, fs} : double4{c.x, c.y, c.z, fs};
 }
 
-// Run the recursion over the degrees lc .. lc+LC-1, writing cf.w * mu (0 while
-// the lane's scale k < 0, and cf.w = 0 outside [l0, lmax]) to out[t * stride].
+// Run the recursion over the degrees lc .. lc+LC-1, writing mu (SCALE: times
+// cf.w, i.e. c f_l mu = c lambda) to out[row(t) * stride]; 0 while the lane's
+// scale k < 0 and outside [l0, lmax].  Without SCALE the caller applies f_l on
+// the side of the product with fewer values per degree.
 // Row of degree offset t in the chunk: natural order, or (PSPLIT) the even
 // offsets first and then the odd ones.
 template <int LC, bool PSPLIT>
@@ -162,7 +164,7 @@ __device__ __forceinline__ int chunk_row(int t)
     return PSPLIT ? (t & 1) * (LC / 2) + (t >> 1) : t;
 }
 
-template <typename T, int LC, bool PSPLIT = false>
+template <typename T, int LC, bool PSPLIT, bool SCALE>
 __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, bool diff, bool slow,
                                    int l0, int lc, int lmax, T *out, int stride, double thr,
                                    double down)
@@ -171,7 +173,8 @@ __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, boo
 #pragma unroll 4
         for (int t = 0; t < LC; ++t) {
             const int l = lc + t;
-            out[chunk_row<LC, PSPLIT>(t) * stride] = (l >= l0 && l <= lmax) ? (T)(c.mu * cf[t].w) : (T)0;
+            out[chunk_row<LC, PSPLIT>(t) * stride] =
+                (l >= l0 && l <= lmax) ? (T)(SCALE ? c.mu * cf[t].w : c.mu) : (T)0;
             if (l >= l0 && l < lmax) {
                 const double4 q = cf[t];
                 if (diff) {
@@ -190,7 +193,7 @@ __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, boo
         for (int t = 0; t < LC; ++t) {
             const int l = lc + t;
             out[chunk_row<LC, PSPLIT>(t) * stride] =
-                (l >= l0 && l <= lmax && c.k == 0) ? (T)(c.mu * cf[t].w) : (T)0;
+                (l >= l0 && l <= lmax && c.k == 0) ? (T)(SCALE ? c.mu * cf[t].w : c.mu) : (T)0;
             if (l >= l0 && l < lmax) {
                 const double4 q = cf[t];
                 if (diff) {
@@ -215,7 +218,7 @@ __device__ inline void chain_chunk(Chain &c, const double4 *__restrict__ cf, boo
 
 // Fast path of chain_chunk: every degree of the chunk lies in [l0, lmax) and
 // every lane of the wavefront already has k = 0 (no masking, no rescaling).
-template <typename T, int LC, bool PSPLIT = false>
+template <typename T, int LC, bool PSPLIT, bool SCALE>
 __device__ __forceinline__ void chain_chunk_fast(Chain &c, const double4 *__restrict__ cf, bool diff,
                                                  T *out, int stride)
 {
@@ -223,7 +226,7 @@ __device__ __forceinline__ void chain_chunk_fast(Chain &c, const double4 *__rest
 #pragma unroll
         for (int t = 0; t < LC; ++t) {
             const double4 q = cf[t];
-            out[chunk_row<LC, PSPLIT>(t) * stride] = (T)(c.mu * q.w);
+            out[chunk_row<LC, PSPLIT>(t) * stride] = (T)(SCALE ? c.mu * q.w : c.mu);
             const double eps = fma(q.x, c.ms2, q.z);
             c.aux = fma(eps, c.mu, c.aux);
             c.mu += c.aux;
@@ -232,7 +235,7 @@ __device__ __forceinline__ void chain_chunk_fast(Chain &c, const double4 *__rest
 #pragma unroll
         for (int t = 0; t < LC; ++t) {
             const double4 q = cf[t];
-            out[chunk_row<LC, PSPLIT>(t) * stride] = (T)(c.mu * q.w);
+            out[chunk_row<LC, PSPLIT>(t) * stride] = (T)(SCALE ? c.mu * q.w : c.mu);
             const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
             c.aux = c.mu;
             c.mu = nx;
@@ -406,9 +409,10 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         }
         T *out = &lam[0][lane];
         if (!slow && lc >= l0 && lc + LC <= lmax) {
-            chain_chunk_fast<T, LC>(cs, cfs[buf][rchain], diff, out, SYN_ROW);
+            chain_chunk_fast<T, LC, false, true>(cs, cfs[buf][rchain], diff, out, SYN_ROW);
         } else {
-            chain_chunk<T, LC>(cs, cfs[buf][rchain], diff, slow, l0, lc, lmax, out, SYN_ROW, thr, down);
+            chain_chunk<T, LC, false, true>(cs, cfs[buf][rchain], diff, slow, l0, lc, lmax, out, SYN_ROW, thr,
+                                            down);
             slow = wave_any(cs.k < 0);
         }
         __syncthreads();
@@ -593,6 +597,7 @@ struct AnaShared {
     static constexpr int REG_D = ((LAMB > NOUTB ? LAMB : NOUTB) + 7) / 8;
     double smem[LEG_NW * REG_D];
     double4 cfs[LEG_NW][SPIN ? 2 : 1][ANA_LC];
+    double fls[ANA_LC];   // c f_l of the chunk's degrees (c = 1/2 for spin 2), applied to the sums
 };
 
 template <int SPIN, int NCB, bool F32>
@@ -753,19 +758,22 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
             for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = V{0, 0, 0, 0};
-            if (active) {
-                {
-                    const int l = lc + (lane % LC);
+            {
+                const int l = lc + (lane % LC);
+                const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) : 0.0;
+                if (wave == 0 && lane < LC) sh.fls[lane] = f;
+                if (active) {
                     const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
-                    const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) : 0.0;
                     if (lane < NCH * LC) cfs[wave][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
                 }
-                if (lc + LC <= lmax) loadC(lc + LC);
+            }
+            if (lc + LC <= lmax) loadC(lc + LC);
+            if (active) {
                 wave_sync();
                 if (!slow && lc >= l0 && lc + LC <= lmax) {
-                    chain_chunk_fast<T, LC, true>(cs, cfs[wave][rchain], diff, lam_out, LDP);
+                    chain_chunk_fast<T, LC, true, false>(cs, cfs[wave][rchain], diff, lam_out, LDP);
                 } else {
-                    chain_chunk<T, LC, true>(cs, cfs[wave][rchain], diff, slow, l0, lc, lmax, lam_out, LDP,
+                    chain_chunk<T, LC, true, false>(cs, cfs[wave][rchain], diff, slow, l0, lc, lmax, lam_out, LDP,
                                              thr, down);
                     slow = wave_any(cs.k < 0);
                 }
@@ -816,6 +824,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 double s = 0.0;
 #pragma unroll
                 for (int w = 0; w < LEG_NW; ++w) s += smem[w * REG_D + e];
+                s *= sh.fls[oloff[j]];
                 if (grad && m > 0) s *= 2.0;   // fac_m of the real-field gradient
                 if (m == 0 && oreim[j]) s = 0.0;
                 obase[j][2 * (int64_t)l] = first ? s : pold[j] + s;
