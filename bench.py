@@ -15,8 +15,10 @@ sample of the same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +29,14 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
 
+# HBM traffic of the dominant kernel, summarised from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE) of this benchmark; only used while the
+# kernel sources hash to what they were when the counters were taken.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "legendre_anal_gl4095s2_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_4945_amd", "csrc", f)
+                  for f in ("legendre.hip", "sht_internal.h")] + \
+                 [os.path.join(ROOT, "paper_1303_4945_amd", "build.py")]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -35,9 +45,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-rings", type=int, default=16)
-    ap.add_argument("--cpu-ms", type=int, default=16)
-    ap.add_argument("--cpu-ntrans", type=int, default=4)
+    ap.add_argument("--cpu-rings", type=int, default=8)
+    ap.add_argument("--cpu-ms", type=int, default=8)
+    ap.add_argument("--cpu-ntrans", type=int, default=2)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, run a plain device copy of this many MiB three "
+                         "times (calibrates the HBM byte counters of a --pmc profile)")
     return ap.parse_args()
 
 
@@ -48,6 +61,42 @@ def log(*a):
 def rel_err(x, ref):
     d = np.max(np.abs(ref))
     return float(np.max(np.abs(x - ref)) / (d if d > 0 else 1.0))
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """Bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is absent or the kernel changed since."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"<!-- traffic (\{.*?\}) -->", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != kernel_sources_hash():
+        return None
+    return rec
+
+
+def copy_probe(mib):
+    """A plain streaming kernel of known size: reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def time_pairs(plan, alm, steps, warmup):
@@ -95,7 +144,6 @@ def cpu_baseline(g, lmax, spin, a, nrings, nms, ntrans_s, G64map, G64alm, G32map
     `nms` m values for the first `ntrans_s` transforms; scaled to whole pairs."""
     import oracle
     oracle.build(force=False)
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rings = np.linspace(0, g.nrings - 1, nrings).round().astype(int)
     ms = np.linspace(0, lmax, nms).round().astype(int)
     sub = np.ascontiguousarray(a[:ntrans_s])
@@ -107,8 +155,8 @@ def cpu_baseline(g, lmax, spin, a, nrings, nms, ntrans_s, G64map, G64alm, G32map
     ref_alm = oracle.analysis(g, lmax, lmax, spin, G64map[:ntrans_s], ms=ms)
     t2 = time.perf_counter()
     ts, ta = t1 - t0, t2 - t1
-    used = min(nthreads, max(nrings, nms))
-    # per-item time on `used` threads -> whole pair of all transforms
+    used = 1  # the oracle is single-threaded C
+    # per-item time -> whole pair of all transforms
     ntr = a.shape[0]
     t_pair = (ts / nrings * g.nrings + ta / nms * (lmax + 1)) * (ntr / ntrans_s)
     # sampled parity
@@ -151,7 +199,8 @@ def main():
     geom = sht.Geometry.from_inputs(g)
     alm = torch.from_numpy(a).to("cuda:0")
 
-    res = {}
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
     t = time.perf_counter()
     p64 = sht.Plan(geom, lmax, spin=spin, ntrans=ntrans, precision="fp64")
     log(f"fp64 plan in {time.perf_counter() - t:.2f} s")
@@ -159,11 +208,14 @@ def main():
     log(f"fp64: {ms64:.1f} ms/pair-step  kernels {k64}")
     map64_h = map64.cpu().numpy()
     alm64_h = alm64.cpu().numpy()
-    flops64 = p64.flops(sht.ALM2MAP)[0]
+    flops64 = {"legendre_synth": p64.flops(sht.ALM2MAP)[0],
+               "legendre_anal": p64.flops(sht.MAP2ALM)[0]}
     del map64, alm64
     map32_h = alm32_h = None
     if not args.no_fp32:
         p32 = sht.Plan(geom, lmax, spin=spin, ntrans=ntrans, precision="fp32_mfma")
+        flops32 = {"legendre_synth": p32.flops(sht.ALM2MAP)[0],
+                   "legendre_anal": p32.flops(sht.MAP2ALM)[0]}
         ms32, k32, map32, alm32 = time_pairs(p32, alm, args.steps, args.warmup)
         log(f"fp32: {ms32:.1f} ms/pair-step  kernels {k32}")
         map32_h = map32.cpu().numpy()
@@ -172,7 +224,12 @@ def main():
     torch.cuda.empty_cache()
 
     dom = max(("legendre_synth", "legendre_anal"), key=lambda n: k64[n])
-    achieved = flops64 / (k64[dom] * 1e-3)
+    achieved = flops64[dom] / (k64[dom] * 1e-3)
+    # the Legendre kernels read or write each phase and each a_lm once
+    ncomp = 2 if spin else 1
+    leg_bytes = 16.0 * ntrans * ncomp * (g.nrings * (lmax + 1) + (lmax + 1) * (lmax + 2) // 2)
+    tr = profiled_traffic()
+    traffic = tr["bytes_per_launch"] if tr and tr.get("kernel") == dom else None
     out = {
         "metric": "alm2map+map2alm pairs/sec at lmax=4095; FP32-MFMA vs FP64 speedup at 1e-6",
         "value": ntrans / (ms64 * 1e-3),
@@ -192,13 +249,16 @@ def main():
         "kernels_ms": {"fp64": k64},
         "roofline": {"bound": "mfma", "kernel": f"{dom} (fp64)", "achieved": achieved / 1e12,
                      "peak": PEAK["fp64_mfma"] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64_mfma"], "traffic": None,
-                     "flops_per_launch": flops64},
+                     "frac": achieved / PEAK["fp64_mfma"], "traffic": traffic,
+                     "flops_per_launch": flops64[dom],
+                     "algorithmic_bytes_per_launch": leg_bytes},
     }
     if not args.no_fp32:
         out["kernels_ms"]["fp32_mfma"] = k32
         out["fp32_mfma"] = {"value": ntrans / (ms32 * 1e-3), "unit": "pairs/s", "ms_per_step": ms32,
                             "speedup_vs_fp64": ms64 / ms32,
+                            "legendre_tflops": {n: flops32[n] / (k32[n] * 1e-3) / 1e12
+                                                for n in flops32},
                             "max_rel_err_map_vs_fp64": rel_err(map32_h, map64_h),
                             "max_rel_err_alm_vs_fp64": rel_err(alm32_h, alm64_h)}
     if not args.no_cpu_baseline:

@@ -564,6 +564,10 @@ __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__re
 // ---------------------------------------------------------------- analysis
 
 constexpr int ANA_LC = 32;   // degrees per chunk (16 per parity class)
+// slot tiles per wavefront and pass: two, except where the stationary phases
+// of two 64-slot tiles and 32 columns would not fit the registers
+template <int SPIN, int NCB>
+constexpr int ana_tpw() { return (SPIN == 0 && NCB == 2) ? 1 : 2; }
 
 // Orders the LDS traffic of one wavefront at this point (the LDS executes a
 // wavefront's requests in issue order; this keeps the compiler from moving
@@ -576,13 +580,16 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Work group = one m and a group of transforms.  The m's active slot tiles are
-// taken LEG_NW at a time (one per wavefront).  Each wavefront runs the
-// recursion of its own tile (lane = chain * 32 + slot, or slot) into its own
-// LDS region, multiplies lambda^T (16 degrees of one parity x 4 slots) with
-// the tile's phases held in registers as G_t +- G_(pi-t) on 16x16x4 matrix-core
-// tiles, and leaves its partial sums in the same region; after one work-group
-// barrier the partial sums of the wavefronts are added in a fixed order and
-// accumulated into a_lm (deterministic, no atomics).
+// taken LEG_NW * TPW at a time (TPW per wavefront).  For every chunk of
+// degrees each wavefront runs the recursion of one of its tiles (lane =
+// chain * 32 + slot, or slot) into its own LDS region, multiplies lambda^T (16
+// degrees of one parity x 4 slots) with that tile's phases held in registers
+// as G_t +- G_(pi-t) on 16x16x4 matrix-core tiles, and repeats for its next
+// tile into the same accumulators; it then leaves its partial sums in the same
+// region, and after one work-group barrier the partial sums of the wavefronts
+// are added in a fixed order and accumulated into a_lm (deterministic, no
+// atomics).  Every pass over the tiles reads and writes the m's a_lm once, so
+// TPW > 1 divides that traffic by TPW at the cost of registers.
 template <int SPIN, bool F32>
 struct AnaShape {
     static constexpr int SPT = SPIN ? 32 : 64;
@@ -600,7 +607,7 @@ struct AnaShared {
     double fls[ANA_LC];   // c f_l of the chunk's degrees (c = 1/2 for spin 2), applied to the sums
 };
 
-template <int SPIN, int NCB, bool F32>
+template <int SPIN, int NCB, bool F32, int TPW>
 __device__ __forceinline__ void anal_item(const LegView &v, const int m, const int t0,
                                           const double *__restrict__ phase, double *__restrict__ alm,
                                           int grad, AnaShared<SPIN, NCB, F32> &sh)
@@ -641,21 +648,23 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     const int rchain = SPIN ? (lane >> 5) : 0;
     T *lam_out = lam_w + rchain * LC * LDP + rslot;
 
-    // this thread's output elements of a chunk: element e -> (transform, component,
-    // degree offset, re/im), consecutive e consecutive in memory
-    double *obase[OPT];
-    int oloff[OPT], oreim[OPT];
+    // this thread's output elements of a chunk: element e = tid + j NT ->
+    // (row tc = transform * NCOMP + component, degree offset, re/im), consecutive
+    // e consecutive in memory.  The degree offset and re/im do not depend on j,
+    // and the row advances by TCS per j.
+    static_assert((NT / 2) % LC == 0, "output element mapping");
+    constexpr int TCS = NT / 2 / LC;
+    const int oreim = tid & 1, oloff = (tid >> 1) % LC, tc0 = (tid >> 1) / LC;
+    unsigned ovalid = 0;   // bit j: element j exists (row in this group, transform < ntrans)
 #pragma unroll
     for (int j = 0; j < OPT; ++j) {
-        const int e = tid + j * NT;
-        const int reim = e & 1;
-        const int loff = (e >> 1) % LC;
-        const int tc = (e >> 1) / LC;
-        const int t = t0 + tc / NCOMP, comp = tc % NCOMP;
-        oreim[j] = reim;
-        oloff[j] = (e < NOUT && t < v.ntrans) ? loff : -1000000;
-        obase[j] = alm + (((int64_t)(t < v.ntrans ? t : 0) * NCOMP + comp) * v.nalm + mbase) * 2 + reim;
+        const int tc = tc0 + TCS * j;
+        if (tc < NCOL / 2 && t0 + tc / NCOMP < v.ntrans) ovalid |= 1u << j;
     }
+    const int64_t ostride = (int64_t)TCS * v.nalm * 2;
+    // row tc0 of this group (only dereferenced for valid elements; loads of
+    // invalid ones go to the start of alm instead)
+    double *const obase = alm + (((int64_t)t0 * NCOMP + tc0) * v.nalm + mbase) * 2 + oreim;
 
     // degrees below l0 (spin 2 with m < 2) are zero by convention
     for (int e = tid; e < 2 * NCOMP * (NCOL / CPJ) * 2; e += NT) {
@@ -671,67 +680,71 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     for (int t = 0; t < v.ntiles; ++t) ntiles_act += v.tile_mlim[t] >= m;
     int tcount = 0, tscan = 0;
     bool first = true;
+    const bool xneg = SPIN && ((i16 & 3) == 0 || (i16 & 3) == 3);
     while (tcount < ntiles_act || first) {
-        int ptile = -1;    // this wavefront's tile in this pass
+        int ptile[TPW];    // this wavefront's tiles in this pass (-1: none)
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) ptile[i] = -1;
         {
             int k = 0;
-            for (; tscan < v.ntiles && k < LEG_NW; ++tscan) {
+            for (; tscan < v.ntiles && k < LEG_NW * TPW; ++tscan) {
                 if (v.tile_mlim[tscan] < m) continue;
-                if (k == wave) ptile = tscan;
+#pragma unroll
+                for (int i = 0; i < TPW; ++i)
+                    if (k == i * LEG_NW + wave) ptile[i] = tscan;
                 ++k;
             }
             tcount += k;
         }
-        const bool active = ptile >= 0;
-        const int slot0 = active ? ptile * SPT : 0;
         // stationary phase fragments B[kk][j] for slot 4 ks + kk and column j + 16 cb:
-        // gw[q] multiplies W (spin 2) or lambda (spin 0) rows; q = 0: G_t + G_(pi-t),
-        // q = 1: G_t - G_(pi-t).  For output o the X rows take sigma_o times the W
-        // operand of column 3 - o, sigma = (-, +, +, -): formed when needed by a
-        // lane exchange within the four columns of a transform.
+        // gw[i][q] multiplies W (spin 2) or lambda (spin 0) rows of tile i; q = 0:
+        // G_t + G_(pi-t), q = 1: G_t - G_(pi-t).  For output o the X rows take
+        // sigma_o times the W operand of column 3 - o, sigma = (-, +, +, -): formed
+        // when needed by a lane exchange within the four columns of a transform.
         // (all loads unconditional from clamped addresses, so that they are
         // issued together rather than one conditional block at a time)
-        T gw[2][KSA][NCB];
-        const bool xneg = SPIN && ((i16 & 3) == 0 || (i16 & 3) == 3);
-        int ynv[KSA], ysv[KSA];
+        T gw[TPW][2][KSA][NCB];
+        Chain cs[TPW];
+        bool diff[TPW], slow[TPW];
 #pragma unroll
-        for (int ks = 0; ks < KSA; ++ks) {
-            const int slot = slot0 + 4 * ks + kk;     // < ntiles * SPT (tables padded)
-            const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
-            const bool ok = active && slot < v.nslots;
-            ynv[ks] = ok ? yn : -1;
-            ysv[ks] = ok ? ys : -1;
-        }
+        for (int i = 0; i < TPW; ++i) {
+            const bool active = ptile[i] >= 0;
+            const int slot0 = active ? ptile[i] * SPT : 0;
+            int ynv[KSA], ysv[KSA];
 #pragma unroll
-        for (int ks = 0; ks < KSA; ++ks) {
-            const int yn = ynv[ks], ys = ysv[ks];
+            for (int ks = 0; ks < KSA; ++ks) {
+                const int slot = slot0 + 4 * ks + kk;     // < ntiles * SPT (tables padded)
+                const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
+                const bool ok = active && slot < v.nslots;
+                ynv[ks] = ok ? yn : -1;
+                ysv[ks] = ok ? ys : -1;
+            }
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                const int col = i16 + 16 * cb;
-                const int tl = col / CPJ, o = col % CPJ;
-                const int t = t0 + tl;
-                auto gval = [&](int oo, double &gsum, double &gdif) {
-                    const int comp = SPIN ? (oo >> 1) : 0, reim = oo & 1;
+            for (int ks = 0; ks < KSA; ++ks) {
+                const int yn = ynv[ks], ys = ysv[ks];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const int col = i16 + 16 * cb;
+                    const int tl = col / CPJ, o = col % CPJ;
+                    const int t = t0 + tl;
+                    const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                     const bool tok = t < v.ntrans;
                     const int64_t rowbase = ((int64_t)(tok ? t : 0) * NCOMP + comp) * v.nrings;
                     const double gn0 = phase[((rowbase + (yn >= 0 ? yn : 0)) * (v.mmax + 1) + m) * 2 + reim];
                     const double gs0 = phase[((rowbase + (ys >= 0 ? ys : 0)) * (v.mmax + 1) + m) * 2 + reim];
                     const double gn = (tok && yn >= 0) ? gn0 : 0.0;
                     const double gs = (tok && ys >= 0) ? gs0 : 0.0;
-                    gsum = gn + gs;
-                    gdif = gn - gs;
-                };
-                double a, b;
-                gval(o, a, b);
-                const double sg = SPIN ? -1.0 : 1.0;
-                gw[0][ks][cb] = (T)(sg * a);
-                gw[1][ks][cb] = (T)(sg * b);
+                    const double sg = SPIN ? -1.0 : 1.0;
+                    gw[i][0][ks][cb] = (T)(sg * (gn + gs));
+                    gw[i][1][ks][cb] = (T)(sg * (gn - gs));
+                }
             }
+            cs[i] = chain_init(v, m, active ? ptile[i] * SPT + rslot : v.nslots, rchain);
+            diff[i] = wave_any(cs[i].x > DIFF_FORM_COS);
+            if (diff[i]) cs[i].aux = cs[i].mu;
+            slow[i] = wave_any(cs[i].k < 0);
         }
-        Chain cs = chain_init(v, m, active ? ptile * SPT + rslot : v.nslots, rchain);
-        const bool diff = wave_any(cs.x > DIFF_FORM_COS);
-        if (diff) cs.aux = cs.mu;
-        bool slow = wave_any(cs.k < 0);
+        const bool any_active = ptile[0] >= 0;   // tiles are dealt to slot 0 first
         // step coefficients of this lane's (chain, degree) entry, loaded one
         // chunk ahead from a clamped address and masked when staged
         double4 c0n = double4{0, 0, 0, 0};
@@ -748,9 +761,10 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
             if (!first) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
-                    const int l = lc + oloff[j];
+                    const int l = lc + oloff;
                     const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
-                    pold[j] = obase[j][2 * (int64_t)lcl];   // used only where l is in range
+                    const double *src = ((ovalid >> j) & 1) ? obase + j * ostride : alm;
+                    pold[j] = src[2 * (int64_t)lcl];   // used only where l is in range
                 }
             }
             V acc[2][NCB];   // [class][column block]
@@ -762,20 +776,22 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 const int l = lc + (lane % LC);
                 const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) : 0.0;
                 if (wave == 0 && lane < LC) sh.fls[lane] = f;
-                if (active) {
+                if (any_active) {
                     const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
                     if (lane < NCH * LC) cfs[wave][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
                 }
             }
             if (lc + LC <= lmax) loadC(lc + LC);
-            if (active) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+                if (ptile[i] < 0) continue;
                 wave_sync();
-                if (!slow && lc >= l0 && lc + LC <= lmax) {
-                    chain_chunk_fast<T, LC, true, false>(cs, cfs[wave][rchain], diff, lam_out, LDP);
+                if (!slow[i] && lc >= l0 && lc + LC <= lmax) {
+                    chain_chunk_fast<T, LC, true, false>(cs[i], cfs[wave][rchain], diff[i], lam_out, LDP);
                 } else {
-                    chain_chunk<T, LC, true, false>(cs, cfs[wave][rchain], diff, slow, l0, lc, lmax, lam_out, LDP,
-                                             thr, down);
-                    slow = wave_any(cs.k < 0);
+                    chain_chunk<T, LC, true, false>(cs[i], cfs[wave][rchain], diff[i], slow[i], l0, lc, lmax,
+                                                    lam_out, LDP, thr, down);
+                    slow[i] = wave_any(cs[i].k < 0);
                 }
                 wave_sync();
 #pragma unroll
@@ -786,21 +802,21 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                         if constexpr (SPIN == 0) {
                             const T a = lam_w[(p * (LC / 2) + i16) * LDP + 4 * ks + kk];
 #pragma unroll
-                            for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = mfma(a, gw[p][ks][cb], acc[p][cb]);
+                            for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = mfma(a, gw[i][p][ks][cb], acc[p][cb]);
                         } else {
                             const T up = lam_w[(0 * LC + p * (LC / 2) + i16) * LDP + 4 * ks + kk];
                             const T um = lam_w[(1 * LC + p * (LC / 2) + i16) * LDP + 4 * ks + kk];
                             const T aw = up + um, ax = up - um;
 #pragma unroll
                             for (int cb = 0; cb < NCB; ++cb) {
-                                acc[p][cb] = mfma(aw, gw[p][ks][cb], acc[p][cb]);
-                                const T q = quad_rev(gw[1 - p][ks][cb]);
+                                acc[p][cb] = mfma(aw, gw[i][p][ks][cb], acc[p][cb]);
+                                const T q = quad_rev(gw[i][1 - p][ks][cb]);
                                 acc[p][cb] = mfma(ax, xneg ? -q : q, acc[p][cb]);
                             }
                         }
                     }
                 }
-                wave_sync();   // lambda reads issued: the region now takes the partial sums
+                wave_sync();   // lambda reads issued: the region takes the next tile or the partial sums
             }
 #pragma unroll
             for (int p = 0; p < 2; ++p)
@@ -813,21 +829,21 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                         const int tl = col / CPJ, o = col % CPJ;
                         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                         const int e = (((tl * NCOMP + comp) * LC) + p + 2 * row) * 2 + reim;
-                        part_w[e] = active ? (double)acc[p][cb][r] : 0.0;
+                        part_w[e] = any_active ? (double)acc[p][cb][r] : 0.0;
                     }
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int e = tid + j * NT;
-                const int l = lc + oloff[j];
-                if (e >= NOUT || l < l0 || l > lmax) continue;
+                const int l = lc + oloff;
+                if (!((ovalid >> j) & 1) || l < l0 || l > lmax) continue;
                 double s = 0.0;
 #pragma unroll
                 for (int w = 0; w < LEG_NW; ++w) s += smem[w * REG_D + e];
-                s *= sh.fls[oloff[j]];
+                s *= sh.fls[oloff];
                 if (grad && m > 0) s *= 2.0;   // fac_m of the real-field gradient
-                if (m == 0 && oreim[j]) s = 0.0;
-                obase[j][2 * (int64_t)l] = first ? s : pold[j] + s;
+                if (m == 0 && oreim) s = 0.0;
+                obase[j * ostride + 2 * (int64_t)l] = first ? s : pold[j] + s;
             }
             __syncthreads();
         }
@@ -842,7 +858,7 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
                                                                   int jobs_per_group, int grad)
 {
     __shared__ AnaShared<SPIN, NCB, F32> sh;
-    anal_item<SPIN, NCB, F32>(v, mlist[blockIdx.x], (int)blockIdx.y * jobs_per_group, phase, alm, grad, sh);
+    anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(v, mlist[blockIdx.x], (int)blockIdx.y * jobs_per_group, phase, alm, grad, sh);
 }
 
 // Persistent form for a batch of plans (one queue, atomic counter).
@@ -861,7 +877,7 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal_batch(const Le
         __syncthreads();
         if (idx >= (unsigned)nitems) break;
         const BatchAnaItem bi = items[idx];
-        anal_item<SPIN, NCB, F32>(views[bi.plan], bi.m, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], grad, sh);
+        anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(views[bi.plan], bi.m, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], grad, sh);
         __syncthreads();
     }
 }

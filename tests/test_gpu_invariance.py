@@ -1,0 +1,113 @@
+"""Invariances of the method and sampled parity at the full workload sizes.
+
+* Polar skipping (Sect. 3.3, Eqs. 7-8) is meant to leave the result unchanged:
+  with and without it the transforms agree to rounding level.
+* The extended exponent step S (rescale_bits) only moves where values are
+  scaled by powers of two; values below 2^-(S/2) are dropped, so S = 128 ..
+  640 agree to rounding level and S = 64 to ~1e-9.
+* Full-size workloads in the launch configuration of the benchmark: the
+  outputs are compared with the oracle on sampled rings (synthesis: every
+  ring is independent) and sampled m (analysis: every m is independent).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sht_inputs as si
+from gpu_util import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def _sht():
+    import paper_1303_4945_amd as sht
+    return sht
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_polar_skip_does_not_change_results(spin):
+    sht = _sht()
+    lmax = 383
+    g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
+    geom = sht.Geometry.from_inputs(g)
+    a = to_dev(si.random_alm(lmax, lmax, 2, spin, tag=41))
+    on = sht.Plan(geom, lmax, spin=spin, ntrans=2)
+    off = sht.Plan(geom, lmax, spin=spin, ntrans=2, polar=False)
+    assert on.flops()[0] < 0.97 * off.flops()[0], "the polar criterion skipped nothing"
+    m_on, m_off = to_host(on.alm2map(a)), to_host(off.alm2map(a))
+    assert rel_err(m_on, m_off) < 1e-13
+    mp = to_dev(m_off)
+    assert rel_err(to_host(on.map2alm(mp)), to_host(off.map2alm(mp))) < 1e-13
+
+
+def test_rescale_step_invariance():
+    sht = _sht()
+    lmax = 1023
+    g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
+    geom = sht.Geometry.from_inputs(g)
+    a = to_dev(si.random_alm(lmax, lmax, 1, 2, tag=42))
+    ref = to_host(sht.Plan(geom, lmax, spin=2, rescale_bits=256).alm2map(a))
+    for bits in (128, 400, 640):
+        got = to_host(sht.Plan(geom, lmax, spin=2, rescale_bits=bits).alm2map(a))
+        assert rel_err(got, ref) < 1e-13, bits
+    got = to_host(sht.Plan(geom, lmax, spin=2, rescale_bits=64).alm2map(a))
+    assert rel_err(got, ref) < 1e-9
+
+
+def _sampled_synthesis_check(g, lmax, spin, a_host, maps_host, rings, trans):
+    ref = oracle.synthesis(g, lmax, lmax, spin, np.ascontiguousarray(a_host[trans]), rings=rings)
+    pix = np.concatenate([np.arange(g.ofs[y], g.ofs[y] + g.nphi[y]) for y in rings])
+    return rel_err(maps_host[trans][..., pix], ref[..., pix])
+
+
+def _sampled_analysis_check(g, lmax, spin, maps_host, alm_host, ms, trans):
+    ref = oracle.analysis(g, lmax, lmax, spin, np.ascontiguousarray(maps_host[trans]), ms=ms)
+    sel = np.concatenate([np.arange(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+                          for m in ms])
+    return rel_err(alm_host[trans][:, :, sel], ref[:, :, sel])
+
+
+@pytest.mark.timeout(300)
+def test_gl4095_spin2_workload_sampled():
+    """Gauss-Legendre 4096 x 8191, lmax 4095, 16 spin-2 transforms (the
+    benchmark's workload and plan), FP64 and FP32-MFMA."""
+    sht = _sht()
+    lmax = 4095
+    g = si.gauss_geometry(4096, 8191)
+    geom = sht.Geometry.from_inputs(g)
+    a = si.random_alm(lmax, lmax, 16, 2)
+    d_a = to_dev(a)
+    p = sht.Plan(geom, lmax, spin=2, ntrans=16)
+    mp = p.alm2map(d_a)
+    back = to_host(p.map2alm(mp))
+    mp_h = to_host(mp)
+    del mp
+    rings = np.array([0, 1, 1000, 2047, 2048, 3500, 4094, 4095])
+    trans = [0, 15]
+    assert _sampled_synthesis_check(g, lmax, 2, a, mp_h, rings, trans) < TOL64
+    ms = np.array([0, 1, 2, 3, 1500, 4094, 4095])
+    assert _sampled_analysis_check(g, lmax, 2, mp_h, back, ms, trans) < TOL64
+    # GL quadrature is exact for this grid: the round trip returns the input
+    assert rel_err(back, a) < 1e-10
+    p32 = sht.Plan(geom, lmax, spin=2, ntrans=16, precision="fp32_mfma")
+    mp32 = to_host(p32.alm2map(d_a))
+    assert rel_err(mp32, mp_h) < 1e-6
+
+
+def test_healpix1024_workload_sampled():
+    """HEALPix N_side = 1024 (4095 rings), lmax 2047, one scalar transform."""
+    sht = _sht()
+    lmax = 2047
+    g = si.healpix_geometry(1024)
+    geom = sht.Geometry.from_inputs(g)
+    a = si.random_alm(lmax, lmax, 1, 0, tag=7)
+    p = sht.Plan(geom, lmax, spin=0, ntrans=1)
+    mp = p.alm2map(to_dev(a))
+    back = to_host(p.map2alm(mp))
+    mp_h = to_host(mp)
+    rings = np.array([0, 1, 2, 511, 1023, 1024, 2047, 3070, 4093, 4094])
+    assert _sampled_synthesis_check(g, lmax, 0, a, mp_h, rings, [0]) < TOL64
+    ms = np.array([0, 1, 2, 700, 1024, 2046, 2047])
+    assert _sampled_analysis_check(g, lmax, 0, mp_h, back, ms, [0]) < TOL64
