@@ -80,7 +80,7 @@ typedef struct sht_plan_opts {
     int rescale_bits;      /* >0: exponent step S of the extended-range recursion
                               (default 256; valid 64..700) */
     int flush_chunks;      /* FP32_MFMA: FP32 partial sums are carried into FP64
-                              after this many 16-degree chunks (default 1) */
+                              after this many 16-degree chunks (default 4) */
     int reserved[8];
 } sht_plan_opts;
 

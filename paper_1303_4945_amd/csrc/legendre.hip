@@ -350,16 +350,29 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
     // meet lambda = 0 in the products, so the values there need no masking
     double R[2][2][NCB], Rn[2][2][NCB];
     auto loadB = [&](int lc, double (&dst)[2][2][NCB]) {
+        if (lc >= l0 && lc + LC <= lmax + 1) {
+            // the whole chunk lies in [l0, lmax]: one address per column block,
+            // the four degrees of this lane at fixed offsets from it
 #pragma unroll
-        for (int par = 0; par < 2; ++par)
+            for (int cb = 0; cb < NCB; ++cb) {
+                const double *p = bp[cb] + 2 * (int64_t)(lc + 2 * kk);
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+                for (int par = 0; par < 2; ++par)
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) {
-                    const int l = lc + 8 * h + 2 * kk + par;
-                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
-                    dst[par][h][cb] = bp[cb][2 * (int64_t)lcl];
-                }
+                    for (int h = 0; h < 2; ++h) dst[par][h][cb] = p[2 * (8 * h + par)];
+            }
+        } else {
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int l = lc + 8 * h + 2 * kk + par;
+                        const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+                        dst[par][h][cb] = bp[cb][2 * (int64_t)lcl];
+                    }
+        }
     };
     double4 c0n = double4{0, 0, 0, 0};
     double f0n = 0.0;

@@ -770,7 +770,7 @@ int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans,
     p->opts = o;
     p->polar_T = o.no_polar_skip ? -1.0 : (o.polar_T > 0 ? o.polar_T : std::max(100.0, 0.01 * lmax));
     p->rescale_bits = o.rescale_bits ? o.rescale_bits : 256;
-    p->flush_chunks = o.flush_chunks ? o.flush_chunks : 1;
+    p->flush_chunks = o.flush_chunks ? o.flush_chunks : 4;
     p->nalm = sht_nalm(lmax, mmax);
     int rc = plan_build(*p);
     if (rc) {

@@ -109,7 +109,7 @@ struct Plan {
     sht_plan_opts opts{};
     double polar_T = 100.0;
     int rescale_bits = 256;
-    int flush_chunks = 1;
+    int flush_chunks = 4;
     int64_t nalm = 0;
     // slots
     std::vector<SlotHost> slots;
