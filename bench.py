@@ -155,8 +155,10 @@ def cpu_baseline(g, lmax, spin, a, nrings, nms, ntrans_s, G64map, G64alm, G32map
     ref_alm = oracle.analysis(g, lmax, lmax, spin, G64map[:ntrans_s], ms=ms)
     t2 = time.perf_counter()
     ts, ta = t1 - t0, t2 - t1
-    used = 1  # the oracle is single-threaded C
-    # per-item time -> whole pair of all transforms
+    # OpenMP over the sampled rings (synthesis) and m values (analysis)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    used = min(nthreads, max(nrings, nms))
+    # wall time per sampled item on `used` threads -> whole pair of all transforms
     ntr = a.shape[0]
     t_pair = (ts / nrings * g.nrings + ta / nms * (lmax + 1)) * (ntr / ntrans_s)
     # sampled parity
