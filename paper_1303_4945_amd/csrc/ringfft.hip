@@ -43,6 +43,7 @@ struct FftInner {       // an in-LDS complex FFT of length n
     int n;
     int nrad;
     int rad[FFT_MAXRAD];
+    int fuse[FFT_MAXRAD];   // 1: pass i runs together with pass i + 1 in registers
     int64_t tw;         // offset of e^{-2 pi i j / n}, j < n
     int64_t pos;        // offset of pos_of_freq[f], f < n
 };
@@ -164,6 +165,27 @@ __device__ __forceinline__ void small_dft(double2 *v, bool fwd, const double2 *t
     }
 }
 
+// Twiddle w = tw[idx] (conjugated for the inverse).  Its powers w^k are
+// formed by repeated multiplication where they are applied (one table load per
+// butterfly; a few ulp of error for the radices used here).
+__device__ __forceinline__ double2 tw_base(const double2 *tw, int idx, bool fwd)
+{
+    const double2 t = tw[idx];
+    return fwd ? t : cconj(t);
+}
+
+// v[j S] *= w^j, j = 1 .. R-1
+template <int R, int S = 1>
+__device__ __forceinline__ void apply_powers(double2 *v, double2 w)
+{
+    double2 p = w;
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+        v[j * S] = cmul(v[j * S], p);
+        if (j + 1 < R) p = cmul(p, w);
+    }
+}
+
 // one pass over the block of length Lb split by radix R (stride Ln = Lb / R)
 template <int R, bool DIT>
 __device__ __forceinline__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
@@ -179,20 +201,13 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, 
         double2 v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) v[j] = buf[PADI(base + j * Ln)];
+        const double2 w = tw_base(tw, tstep * n1, fwd);
         if constexpr (DIT) {
-#pragma unroll
-            for (int j = 1; j < R; ++j) {
-                double2 t = tw[tstep * n1 * j];
-                v[j] = cmul(v[j], fwd ? t : cconj(t));
-            }
+            apply_powers<R>(v, w);
             small_dft<R>(v, fwd, tw, n);
         } else {
             small_dft<R>(v, fwd, tw, n);
-#pragma unroll
-            for (int j = 1; j < R; ++j) {
-                double2 t = tw[tstep * n1 * j];
-                v[j] = cmul(v[j], fwd ? t : cconj(t));
-            }
+            apply_powers<R>(v, w);
         }
 #pragma unroll
         for (int j = 0; j < R; ++j) buf[PADI(base + j * Ln)] = v[j];
@@ -255,13 +270,13 @@ __device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool f
         double2 v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) v[j] = buf[PADI(base + j * Ln)];
-        if constexpr (DIT) {
-#pragma unroll
-            for (int j = 1; j < R; ++j) {
-                double2 t = tw[tstep * n1 * j];
-                v[j] = cmul(v[j], fwd ? t : cconj(t));
-            }
-        }
+        const double2 w = tw_base(tw, tstep * n1, fwd);
+        if constexpr (DIT) apply_powers<R>(v, w);
+        // DIF: outputs k and R - k take w^k and w^(R-k), formed upwards from w
+        // and downwards from w^(R-1)
+        double2 pk = w, qk = make_double2(1.0, 0.0);
+        if constexpr (!DIT) qk = tw_base(tw, tstep * n1 * (R - 1), fwd);
+        const double2 wc = cconj(w);
         const double2 v0 = v[0];
         double2 sum0 = v0;
 #pragma unroll
@@ -289,15 +304,173 @@ __device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool f
             double2 ok = make_double2(A.x + B.y, A.y - B.x);
             double2 okr = make_double2(A.x - B.y, A.y + B.x);
             if constexpr (!DIT) {
-                const double2 t1 = tw[tstep * n1 * k], t2 = tw[tstep * n1 * (R - k)];
-                ok = cmul(ok, fwd ? t1 : cconj(t1));
-                okr = cmul(okr, fwd ? t2 : cconj(t2));
+                ok = cmul(ok, pk);
+                okr = cmul(okr, qk);
+                pk = cmul(pk, w);
+                qk = cmul(qk, wc);
             }
             buf[PADI(base + k * Ln)] = ok;
             buf[PADI(base + (R - k) * Ln)] = okr;
         }
     }
     __syncthreads();
+}
+
+// DFTs in registers over the elements v[j S], j < R (outputs back in place).
+// Odd radices in the symmetric form of fft_pass_odd.
+template <int R, int S>
+__device__ __forceinline__ void dft_odd_reg(double2 *v, bool fwd)
+{
+    constexpr int H = (R - 1) / 2;
+    const double ssign = fwd ? 1.0 : -1.0;
+    double2 sv[H + 1], dv[H + 1];
+    const double2 v0 = v[0];
+    double2 sum0 = v0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        sv[j] = cadd(v[j * S], v[(R - j) * S]);
+        dv[j] = csub(v[j * S], v[(R - j) * S]);
+        sum0 = cadd(sum0, sv[j]);
+    }
+    v[0] = sum0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        double2 A = v0, B = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const int m = (j * k) % R;
+            const double c = (m <= H) ? OddRoots<R>::c[m] : OddRoots<R>::c[R - m];
+            const double sn = ssign * ((m <= H) ? OddRoots<R>::s[m] : -OddRoots<R>::s[R - m]);
+            A.x += sv[j].x * c;
+            A.y += sv[j].y * c;
+            B.x += dv[j].x * sn;
+            B.y += dv[j].y * sn;
+        }
+        v[k * S] = make_double2(A.x + B.y, A.y - B.x);
+        v[(R - k) * S] = make_double2(A.x - B.y, A.y + B.x);
+    }
+}
+
+template <int R, int S>
+__device__ __forceinline__ void dft_reg(double2 *v, bool fwd)
+{
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[S];
+        v[0] = cadd(a, b);
+        v[S] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const double2 a = cadd(v[0], v[2 * S]), b = csub(v[0], v[2 * S]);
+        const double2 c = cadd(v[S], v[3 * S]), d = cmul_mi(csub(v[S], v[3 * S]), fwd);
+        v[0] = cadd(a, c);
+        v[2 * S] = csub(a, c);
+        v[S] = cadd(b, d);
+        v[3 * S] = csub(b, d);
+    } else if constexpr (R == 8) {
+        // radix-4 DFTs of the even and odd elements, then a radix-2 combination
+        dft_reg<4, 2 * S>(v, fwd);
+        dft_reg<4, 2 * S>(v + S, fwd);
+        const double h = 0.70710678118654752440;
+        double2 o1 = v[3 * S], o2 = v[5 * S], o3 = v[7 * S];
+        o1 = fwd ? make_double2(h * (o1.x + o1.y), h * (o1.y - o1.x))
+                 : make_double2(h * (o1.x - o1.y), h * (o1.y + o1.x));
+        o2 = cmul_mi(o2, fwd);
+        o3 = fwd ? make_double2(h * (-o3.x + o3.y), h * (-o3.y - o3.x))
+                 : make_double2(h * (-o3.x - o3.y), h * (-o3.y + o3.x));
+        const double2 e0 = v[0], e1 = v[2 * S], e2 = v[4 * S], e3 = v[6 * S], o0 = v[S];
+        v[0] = cadd(e0, o0);
+        v[4 * S] = csub(e0, o0);
+        v[S] = cadd(e1, o1);
+        v[5 * S] = csub(e1, o1);
+        v[2 * S] = cadd(e2, o2);
+        v[6 * S] = csub(e2, o2);
+        v[3 * S] = cadd(e3, o3);
+        v[7 * S] = csub(e3, o3);
+    } else {
+        dft_odd_reg<R, S>(v, fwd);
+    }
+}
+
+// Two consecutive passes (radix R1 on blocks of Lb, then radix R2 on blocks of
+// Lb / R1) in one sweep: each thread owns the R1 R2 elements
+// base + j LnA + jb LnB (LnA = Lb / R1, LnB = LnA / R2), which both passes
+// combine only among themselves, so the intermediate values stay in registers
+// and the data cross LDS once.  DIT runs the two passes in the reverse order
+// with the twiddles before each DFT.  Same results as fft_pass twice.
+template <int R1, int R2, bool DIT>
+__device__ __forceinline__ void fft_pass2(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
+{
+    const int LnA = Lb / R1;
+    const int LnB = LnA / R2;
+    const int nb = n / (R1 * R2);
+    const int tA = n / Lb, tB = n / LnA;   // twiddle steps of the two passes
+#pragma unroll 1
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        const int b = q / LnB;
+        const int n1 = q - b * LnB;
+        const int base = b * Lb + n1;
+        // element (j, jb) at v[j R2 + jb]
+        double2 v[R1 * R2];
+#pragma unroll
+        for (int j = 0; j < R1; ++j)
+#pragma unroll
+            for (int jb = 0; jb < R2; ++jb) v[j * R2 + jb] = buf[PADI(base + j * LnA + jb * LnB)];
+        if constexpr (!DIT) {
+#pragma unroll
+            for (int jb = 0; jb < R2; ++jb) {
+                dft_reg<R1, R2>(v + jb, fwd);
+                apply_powers<R1, R2>(v + jb, tw_base(tw, tA * (n1 + jb * LnB), fwd));
+            }
+            const double2 wb = tw_base(tw, tB * n1, fwd);
+#pragma unroll
+            for (int k = 0; k < R1; ++k) {
+                dft_reg<R2, 1>(v + k * R2, fwd);
+                apply_powers<R2, 1>(v + k * R2, wb);
+            }
+        } else {
+            const double2 wb = tw_base(tw, tB * n1, fwd);
+#pragma unroll
+            for (int j = 0; j < R1; ++j) {
+                apply_powers<R2, 1>(v + j * R2, wb);
+                dft_reg<R2, 1>(v + j * R2, fwd);
+            }
+#pragma unroll
+            for (int kb = 0; kb < R2; ++kb) {
+                apply_powers<R1, R2>(v + kb, tw_base(tw, tA * (n1 + kb * LnB), fwd));
+                dft_reg<R1, R2>(v + kb, fwd);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R1; ++k)
+#pragma unroll
+            for (int kb = 0; kb < R2; ++kb) buf[PADI(base + k * LnA + kb * LnB)] = v[k * R2 + kb];
+    }
+    __syncthreads();
+}
+
+// fused pairs that occur (the host orders each pair with R1 >= R2)
+template <bool DIT, bool POW2>
+__device__ __forceinline__ void fft_pass2_any(double2 *buf, int n, int Lb, int r1, int r2, bool fwd,
+                                              const double2 *tw)
+{
+    switch (r1 * 16 + r2) {
+    case 2 * 16 + 2: fft_pass2<2, 2, DIT>(buf, n, Lb, fwd, tw); break;
+    case 4 * 16 + 2: fft_pass2<4, 2, DIT>(buf, n, Lb, fwd, tw); break;
+    case 4 * 16 + 4: fft_pass2<4, 4, DIT>(buf, n, Lb, fwd, tw); break;
+    case 8 * 16 + 2: fft_pass2<8, 2, DIT>(buf, n, Lb, fwd, tw); break;
+    default:
+        if constexpr (!POW2) {
+            switch (r1 * 16 + r2) {
+            case 3 * 16 + 2: fft_pass2<3, 2, DIT>(buf, n, Lb, fwd, tw); break;
+            case 3 * 16 + 3: fft_pass2<3, 3, DIT>(buf, n, Lb, fwd, tw); break;
+            case 4 * 16 + 3: fft_pass2<4, 3, DIT>(buf, n, Lb, fwd, tw); break;
+            case 5 * 16 + 2: fft_pass2<5, 2, DIT>(buf, n, Lb, fwd, tw); break;
+            case 5 * 16 + 3: fft_pass2<5, 3, DIT>(buf, n, Lb, fwd, tw); break;
+            case 7 * 16 + 2: fft_pass2<7, 2, DIT>(buf, n, Lb, fwd, tw); break;
+            default: break;
+            }
+        }
+        break;
+    }
 }
 
 // POW2: only radices 2, 4, 8 occur (keeps the odd-radix code, and its
@@ -330,9 +503,16 @@ __device__ __forceinline__ void fft_dif(double2 *buf, const FftInner &in, bool f
 {
     const double2 *tw = ctab + in.tw;
     int Lb = in.n;
-    for (int i = 0; i < in.nrad; ++i) {
-        fft_pass_any<false, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
-        Lb /= in.rad[i];
+    for (int i = 0; i < in.nrad;) {
+        if (in.fuse[i]) {
+            fft_pass2_any<false, POW2>(buf, in.n, Lb, in.rad[i], in.rad[i + 1], fwd, tw);
+            Lb /= in.rad[i] * in.rad[i + 1];
+            i += 2;
+        } else {
+            fft_pass_any<false, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
+            Lb /= in.rad[i];
+            i += 1;
+        }
     }
 }
 
@@ -342,9 +522,16 @@ __device__ __forceinline__ void fft_dit(double2 *buf, const FftInner &in, bool f
 {
     const double2 *tw = ctab + in.tw;
     int Lb = 1;
-    for (int i = in.nrad - 1; i >= 0; --i) {
-        Lb *= in.rad[i];
-        fft_pass_any<true, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
+    for (int i = in.nrad - 1; i >= 0;) {
+        if (i >= 1 && in.fuse[i - 1]) {
+            Lb *= in.rad[i - 1] * in.rad[i];
+            fft_pass2_any<true, POW2>(buf, in.n, Lb, in.rad[i - 1], in.rad[i], fwd, tw);
+            i -= 2;
+        } else {
+            Lb *= in.rad[i];
+            fft_pass_any<true, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
+            i -= 1;
+        }
     }
 }
 
@@ -756,6 +943,81 @@ static bool factor_smooth(int n, std::vector<int> &rad)
     return m == 1 && (int)rad.size() <= FFT_MAXRAD;
 }
 
+// Pass plan of an inner transform: which consecutive passes run fused in
+// registers (fft_pass2), and in which order.  Fused pairs (larger radix first)
+// keep at most 16 complex values per thread.  The grouping minimises the
+// butterfly rounds a work group of the given size executes, plus one per LDS
+// sweep (each sweep ends in a barrier).  Smaller groups go first: late DIF
+// passes use few distinct twiddles, so the large radices are cheapest there.
+static bool fusable(int r1, int r2)
+{
+    static const int ok[][2] = {{2, 2}, {4, 2}, {4, 4}, {8, 2}, {3, 2}, {3, 3}, {4, 3}, {5, 2}, {5, 3}, {7, 2}};
+    for (const auto &q : ok)
+        if (q[0] == r1 && q[1] == r2) return true;
+    return false;
+}
+
+static int inner_threads(int n)
+{
+    int c = 1;
+    while (c < n) c *= 2;
+    return c >= 8192 ? 1024 : (c >= 2048 ? 512 : 256);
+}
+
+static void best_grouping(int n, int threads, std::vector<int> rest, std::vector<std::vector<int>> &cur,
+                          double &best_cost, std::vector<std::vector<int>> &best)
+{
+    if (rest.empty()) {
+        double cost = 0.0;
+        for (const auto &g : cur) {
+            int prod = 1;
+            for (int r : g) prod *= r;
+            const int nb = n / prod;
+            cost += (double)((nb + threads - 1) / threads) + 1.0;
+        }
+        if (cost < best_cost) { best_cost = cost; best = cur; }
+        return;
+    }
+    const int f = rest[0];
+    std::vector<int> tail(rest.begin() + 1, rest.end());
+    cur.push_back({f});
+    best_grouping(n, threads, tail, cur, best_cost, best);
+    cur.pop_back();
+    for (size_t i = 0; i < tail.size(); ++i) {
+        if (i > 0 && tail[i] == tail[i - 1]) continue;
+        const int a = std::max(f, tail[i]), b = std::min(f, tail[i]);
+        if (!fusable(a, b)) continue;
+        std::vector<int> t2 = tail;
+        t2.erase(t2.begin() + (long)i);
+        cur.push_back({a, b});
+        best_grouping(n, threads, t2, cur, best_cost, best);
+        cur.pop_back();
+    }
+}
+
+static void plan_passes(int n, std::vector<int> &rad, std::vector<int> &fuse)
+{
+    std::vector<int> f = rad;
+    std::sort(f.begin(), f.end());
+    std::vector<std::vector<int>> cur, best;
+    double cost = 1e30;
+    best_grouping(n, inner_threads(n), f, cur, cost, best);
+    std::stable_sort(best.begin(), best.end(), [](const std::vector<int> &x, const std::vector<int> &y) {
+        int px = 1, py = 1;
+        for (int r : x) px *= r;
+        for (int r : y) py *= r;
+        return px < py;
+    });
+    rad.clear();
+    fuse.clear();
+    for (const auto &g : best) {
+        for (size_t i = 0; i < g.size(); ++i) {
+            rad.push_back(g[i]);
+            fuse.push_back(g.size() == 2 && i == 0 ? 1 : 0);
+        }
+    }
+}
+
 static bool is_prime(int n)
 {
     if (n < 2) return false;
@@ -813,10 +1075,14 @@ static int add_inner(FftHost &H, int n)
     if (it != H.inner_of_n.end()) return it->second;
     FftInner in{};
     in.n = n;
-    std::vector<int> rad;
+    std::vector<int> rad, fuse;
     factor_smooth(n, rad);
+    plan_passes(n, rad, fuse);
     in.nrad = (int)rad.size();
-    for (int i = 0; i < in.nrad; ++i) in.rad[i] = rad[i];
+    for (int i = 0; i < in.nrad; ++i) {
+        in.rad[i] = rad[i];
+        in.fuse[i] = fuse[i];
+    }
     in.tw = (int64_t)H.ctab.size();
     for (int j = 0; j < n; ++j) {
         long double a = -2.0L * kPi * (long double)j / (long double)n;
