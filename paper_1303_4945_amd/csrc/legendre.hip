@@ -275,8 +275,9 @@ __device__ __forceinline__ double quad_rev(double x)
 // wavefront itself.
 //
 // Recursion: lane = chain * 32 + slot (spin 2: chain 0 = +2, 1 = -2) or lane =
-// slot (spin 0); each chunk of SYN_LC degrees is written to LDS as
-// c * f_l * mu_l (c = 1/2 for spin 2, 1 for spin 0).
+// slot (spin 0); each chunk of SYN_LC degrees of mu_l is written to LDS, and
+// the factor c f_l (c = 1/2 for spin 2, 1 for spin 0) goes onto the
+// coefficients (four degrees per lane instead of sixteen recursion steps).
 //
 // Products (Eq. 4) on 16x16x4 matrix-core tiles, rows = 16 slots, columns =
 // 16 of the group's (transform, component, re/im) columns, k = 4 degrees of
@@ -388,6 +389,18 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         const double f = (l >= l0 && l <= lmax) ? f0n * fscale : 0.0;
         if (lane < NCH * LC) cfs[buf][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
     };
+    // c f_l onto the coefficients of the chunk staged in cfs[buf] (zero outside
+    // [l0, lmax]): the recursion then writes plain mu
+    auto scaleB = [&](int buf, double (&dst)[2][2][NCB]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                const double f = cfs[buf][0][8 * h + 2 * kk + par].w;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) dst[par][h][cb] *= f;
+            }
+    };
 
     V acc[2][NSB][NCB];
     double acc64[F32 ? 2 : 1][F32 ? NSB : 1][F32 ? NCB : 1][4];
@@ -412,6 +425,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
     loadC(lstart);
     storeC(0, lstart);
     __syncthreads();
+    scaleB(0, R);
     int chunk = 0;
     for (int lc = lstart; lc <= lmax; lc += LC, ++chunk) {
         const int buf = chunk & 1;
@@ -422,9 +436,9 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         }
         T *out = &lam[0][lane];
         if (!slow && lc >= l0 && lc + LC <= lmax) {
-            chain_chunk_fast<T, LC, false, true>(cs, cfs[buf][rchain], diff, out, SYN_ROW);
+            chain_chunk_fast<T, LC, false, false>(cs, cfs[buf][rchain], diff, out, SYN_ROW);
         } else {
-            chain_chunk<T, LC, false, true>(cs, cfs[buf][rchain], diff, slow, l0, lc, lmax, out, SYN_ROW, thr,
+            chain_chunk<T, LC, false, false>(cs, cfs[buf][rchain], diff, slow, l0, lc, lmax, out, SYN_ROW, thr,
                                             down);
             slow = wave_any(cs.k < 0);
         }
@@ -502,6 +516,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
                     for (int cb = 0; cb < NCB; ++cb) R[par][h][cb] = Rn[par][h][cb];
         }
         __syncthreads();
+        if (more) scaleB(buf ^ 1, R);
     }
 
     // ring indices of this lane's output rows, all loaded before any store
