@@ -627,12 +627,19 @@ struct AnaShape {
 };
 template <int SPIN, int NCB, bool F32>
 struct AnaShared {
+    // FP32 form: the partial sums (FP32 products) get a region of their own,
+    // double-buffered by chunk, so one work-group barrier per chunk suffices;
+    // the FP64 partial sums reuse the lambda region (two barriers per chunk)
+    // because a second region would not leave room for two work groups per CU
+    static constexpr bool PSEP = F32;
     static constexpr int LAMB = AnaShape<SPIN, F32>::LAMW * (int)sizeof(typename MT<F32>::T);
-    static constexpr int NOUTB = ANA_LC * NCB * 16 * 8;
-    static constexpr int REG_D = ((LAMB > NOUTB ? LAMB : NOUTB) + 7) / 8;
+    static constexpr int NOUT = ANA_LC * NCB * 16;
+    static constexpr int NOUTB = NOUT * 8;
+    static constexpr int REG_D = ((PSEP ? LAMB : (LAMB > NOUTB ? LAMB : NOUTB)) + 7) / 8;
     double smem[LEG_NW * REG_D];
+    float psum[PSEP ? 2 * LEG_NW * NOUT : 1];
     double4 cfs[LEG_NW][SPIN ? 2 : 1][ANA_LC];
-    double fls[ANA_LC];   // c f_l of the chunk's degrees (c = 1/2 for spin 2), applied to the sums
+    double fls[PSEP ? 2 : 1][ANA_LC];   // c f_l of the chunk's degrees (c = 1/2 for spin 2), applied to the sums
 };
 
 template <int SPIN, int NCB, bool F32, int TPW>
@@ -709,6 +716,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     int tcount = 0, tscan = 0;
     bool first = true;
     const bool xneg = SPIN && ((i16 & 3) == 0 || (i16 & 3) == 3);
+    constexpr bool PSEP = AnaShared<SPIN, NCB, F32>::PSEP;
+    int cidx = 0;   // chunks done (selects the partial-sum buffer)
     while (tcount < ntiles_act || first) {
         int ptile[TPW];    // this wavefront's tiles in this pass (-1: none)
 #pragma unroll
@@ -803,7 +812,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
             {
                 const int l = lc + (lane % LC);
                 const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) : 0.0;
-                if (wave == 0 && lane < LC) sh.fls[lane] = f;
+                if (wave == 0 && lane < LC) sh.fls[PSEP ? (cidx & 1) : 0][lane] = f;
                 if (any_active) {
                     const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
                     if (lane < NCH * LC) cfs[wave][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
@@ -857,7 +866,10 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                         const int tl = col / CPJ, o = col % CPJ;
                         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                         const int e = (((tl * NCOMP + comp) * LC) + p + 2 * row) * 2 + reim;
-                        part_w[e] = any_active ? (double)acc[p][cb][r] : 0.0;
+                        if constexpr (PSEP)
+                            sh.psum[((cidx & 1) * LEG_NW + wave) * NOUT + e] = any_active ? (float)acc[p][cb][r] : 0.0f;
+                        else
+                            part_w[e] = any_active ? (double)acc[p][cb][r] : 0.0;
                     }
             __syncthreads();
 #pragma unroll
@@ -867,13 +879,17 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 if (!((ovalid >> j) & 1) || l < l0 || l > lmax) continue;
                 double s = 0.0;
 #pragma unroll
-                for (int w = 0; w < LEG_NW; ++w) s += smem[w * REG_D + e];
-                s *= sh.fls[oloff];
+                for (int w = 0; w < LEG_NW; ++w) {
+                    if constexpr (PSEP) s += (double)sh.psum[((cidx & 1) * LEG_NW + w) * NOUT + e];
+                    else s += smem[w * REG_D + e];
+                }
+                s *= sh.fls[PSEP ? (cidx & 1) : 0][oloff];
                 if (grad && m > 0) s *= 2.0;   // fac_m of the real-field gradient
                 if (m == 0 && oreim) s = 0.0;
                 obase[j * ostride + 2 * (int64_t)l] = first ? s : pold[j] + s;
             }
-            __syncthreads();
+            if constexpr (!PSEP) __syncthreads();
+            ++cidx;
         }
         first = false;
     }
