@@ -455,16 +455,12 @@ __device__ __forceinline__ void fft_pass2_any(double2 *buf, int n, int Lb, int r
     switch (r1 * 16 + r2) {
     case 2 * 16 + 2: fft_pass2<2, 2, DIT>(buf, n, Lb, fwd, tw); break;
     case 4 * 16 + 2: fft_pass2<4, 2, DIT>(buf, n, Lb, fwd, tw); break;
-    case 4 * 16 + 4: fft_pass2<4, 4, DIT>(buf, n, Lb, fwd, tw); break;
-    case 8 * 16 + 2: fft_pass2<8, 2, DIT>(buf, n, Lb, fwd, tw); break;
     default:
         if constexpr (!POW2) {
             switch (r1 * 16 + r2) {
             case 3 * 16 + 2: fft_pass2<3, 2, DIT>(buf, n, Lb, fwd, tw); break;
             case 3 * 16 + 3: fft_pass2<3, 3, DIT>(buf, n, Lb, fwd, tw); break;
-            case 4 * 16 + 3: fft_pass2<4, 3, DIT>(buf, n, Lb, fwd, tw); break;
             case 5 * 16 + 2: fft_pass2<5, 2, DIT>(buf, n, Lb, fwd, tw); break;
-            case 5 * 16 + 3: fft_pass2<5, 3, DIT>(buf, n, Lb, fwd, tw); break;
             case 7 * 16 + 2: fft_pass2<7, 2, DIT>(buf, n, Lb, fwd, tw); break;
             default: break;
             }
@@ -945,13 +941,14 @@ static bool factor_smooth(int n, std::vector<int> &rad)
 
 // Pass plan of an inner transform: which consecutive passes run fused in
 // registers (fft_pass2), and in which order.  Fused pairs (larger radix first)
-// keep at most 16 complex values per thread.  The grouping minimises the
+// keep at most 14 complex values per thread (with 15 or 16 the 1024-thread
+// kernels spill registers).  The grouping minimises the
 // butterfly rounds a work group of the given size executes, plus one per LDS
 // sweep (each sweep ends in a barrier).  Smaller groups go first: late DIF
 // passes use few distinct twiddles, so the large radices are cheapest there.
 static bool fusable(int r1, int r2)
 {
-    static const int ok[][2] = {{2, 2}, {4, 2}, {4, 4}, {8, 2}, {3, 2}, {3, 3}, {4, 3}, {5, 2}, {5, 3}, {7, 2}};
+    static const int ok[][2] = {{2, 2}, {4, 2}, {3, 2}, {3, 3}, {5, 2}, {7, 2}};
     for (const auto &q : ok)
         if (q[0] == r1 && q[1] == r2) return true;
     return false;
