@@ -107,6 +107,7 @@ class Geometry:
 
     def __init__(self, handle):
         self._h = handle
+        self._destroy = _lib.sht_geom_destroy
         n = ctypes.c_int()
         npix = ctypes.c_int64()
         _check(_lib.sht_geom_info(self._h, ctypes.byref(n), ctypes.byref(npix)))
@@ -155,9 +156,11 @@ class Geometry:
         return dict(theta=th, nphi=nphi, phi0=ph, weight=w, ofs=ofs)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h:
-            _lib.sht_geom_destroy(h)
+        # the destroy function is held by the object: at interpreter exit the
+        # module's globals may already be gone
+        h, fn = getattr(self, "_h", None), getattr(self, "_destroy", None)
+        if h and fn is not None:
+            fn(h)
             self._h = None
 
 
@@ -186,6 +189,7 @@ class Plan:
         _check(_lib.sht_plan_create(geom._h, lmax, mmax, spin, ntrans, precision, ctypes.byref(o),
                                     ctypes.byref(h)))
         self._h = h
+        self._destroy = _lib.sht_plan_destroy
         self.geom = geom
         self.lmax, self.mmax, self.spin, self.ntrans = lmax, mmax, spin, ntrans
         self.precision = precision
@@ -258,9 +262,9 @@ class Plan:
         _check(_lib.sht_autotune(self._h, budget_seconds))
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h:
-            _lib.sht_plan_destroy(h)
+        h, fn = getattr(self, "_h", None), getattr(self, "_destroy", None)
+        if h and fn is not None:
+            fn(h)
             self._h = None
 
 
@@ -276,6 +280,7 @@ class Batch:
         h = _vp()
         _check(_lib.sht_batch_create(len(self.plans), arr, ctypes.byref(h)))
         self._h = h
+        self._destroy = _lib.sht_batch_destroy
 
     def execute(self, direction, ins, outs=None, stream=None):
         import torch
@@ -302,7 +307,7 @@ class Batch:
         return self.execute(MAP2ALM, maps, outs, stream)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h:
-            _lib.sht_batch_destroy(h)
+        h, fn = getattr(self, "_h", None), getattr(self, "_destroy", None)
+        if h and fn is not None:
+            fn(h)
             self._h = None
