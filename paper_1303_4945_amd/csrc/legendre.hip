@@ -28,9 +28,9 @@
 //
 // Analysis (Eq. 5), per m: out[l][col] = sum_slot Lambda[l][slot] G[slot][col]
 // with the ring pair folded into G_t +- G_(pi-t); a work group of LEG_NW
-// wavefronts walks the active tiles LEG_NW at a time, reduces the wavefronts'
-// partial sums in LDS and accumulates them into the output in a fixed order
-// (deterministic, no atomics).
+// wavefronts walks the active tiles LEG_NW * ana_tpw at a time, reduces the
+// wavefronts' partial sums in LDS and accumulates them into the output in a
+// fixed order (deterministic, no atomics).
 #include <hip/hip_runtime.h>
 
 #include "sht_internal.h"
