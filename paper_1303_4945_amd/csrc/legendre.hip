@@ -794,16 +794,6 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
         };
         loadC(lstart);
         for (int lc = lstart; lc <= lmax; lc += LC) {
-            double pold[OPT];
-            if (!first) {
-#pragma unroll
-                for (int j = 0; j < OPT; ++j) {
-                    const int l = lc + oloff;
-                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
-                    const double *src = ((ovalid >> j) & 1) ? obase + j * ostride : alm;
-                    pold[j] = src[2 * (int64_t)lcl];   // used only where l is in range
-                }
-            }
             V acc[2][NCB];   // [class][column block]
 #pragma unroll
             for (int p = 0; p < 2; ++p)
@@ -854,6 +844,18 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                     }
                 }
                 wave_sync();   // lambda reads issued: the region takes the next tile or the partial sums
+            }
+            // the previous passes' sums of this thread's outputs (loaded after the
+            // products, so that they take no registers during them)
+            double pold[OPT];
+            if (!first) {
+#pragma unroll
+                for (int j = 0; j < OPT; ++j) {
+                    const int l = lc + oloff;
+                    const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+                    const double *src = ((ovalid >> j) & 1) ? obase + j * ostride : alm;
+                    pold[j] = src[2 * (int64_t)lcl];   // used only where l is in range
+                }
             }
 #pragma unroll
             for (int p = 0; p < 2; ++p)
