@@ -67,7 +67,8 @@ typedef enum {
 } sht_status;
 
 enum { SHT_FP64 = 0, SHT_FP32_MFMA = 1 };
-enum { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1, SHT_ALM2MAP_ADJOINT = 2, SHT_ALM2MAP_GRAD = 3 };
+enum { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1, SHT_ALM2MAP_ADJOINT = 2, SHT_ALM2MAP_GRAD = 3,
+       SHT_MAP2ALM_ADJOINT = 4 };
 
 typedef struct sht_geom sht_geom;
 typedef struct sht_plan sht_plan;
@@ -130,17 +131,23 @@ void sht_plan_destroy(sht_plan *p);
    the stored coefficients (m >= 0), i.e. fac_m Y^T g with fac_0 = 1 and
    fac_m = 2 for m > 0, because a_{l,-m} = (-1)^m conj(a_lm) enters the map too;
    entries the synthesis ignores (Im a_l0, l < |spin|) get gradient 0.
+   SHT_MAP2ALM_ADJOINT (Sect. 4.5, the adjoint of analysis Y^T W): in = a_lm,
+   out = W Y a, the synthesis with every ring multiplied by its weight w_y
+   (needs weights).  For real maps x the pair satisfies
+   <x, W Y a> = sum over l, m >= 0 of fac_m Re(a_lm conj((Y^T W x)_lm)).
    in and out must not overlap. */
 int sht_execute(sht_plan *p, int direction, const double *in, double *out,
                 void *hip_stream);
 
-/* Legendre step only (Eqs. 4, 5).  SHT_ALM2MAP: in = a_lm, out = F phases.
+/* Legendre step only (Eqs. 4, 5).  SHT_ALM2MAP (and SHT_MAP2ALM_ADJOINT, the
+   same Legendre step): in = a_lm, out = F phases.
    SHT_MAP2ALM / SHT_ALM2MAP_ADJOINT / SHT_ALM2MAP_GRAD: in = G phases, out = a_lm
    (GRAD also applies fac_m). */
 int sht_legendre(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 
 /* Ring FFT step only (Eqs. 3, 6).  SHT_ALM2MAP: in = F phases, out = maps.
+   SHT_MAP2ALM_ADJOINT: in = F phases, out = maps times the ring weights w_y;
    SHT_MAP2ALM: in = maps, out = G phases with weights w_y;
    SHT_ALM2MAP_ADJOINT and SHT_ALM2MAP_GRAD: the same with all weights one. */
 int sht_ring_fft(sht_plan *p, int direction, const double *in, double *out,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_EUNSUPPORTED, SHT_ESTATE = range(6)
 FP64, FP32_MFMA = 0, 1
-ALM2MAP, MAP2ALM, ALM2MAP_ADJOINT, ALM2MAP_GRAD = 0, 1, 2, 3
+ALM2MAP, MAP2ALM, ALM2MAP_ADJOINT, ALM2MAP_GRAD, MAP2ALM_ADJOINT = 0, 1, 2, 3, 4
 
 _STATUS_NAMES = {1: "SHT_EINVAL", 2: "SHT_ENOMEM", 3: "SHT_EDEVICE", 4: "SHT_EUNSUPPORTED",
                  5: "SHT_ESTATE"}
@@ -231,6 +231,10 @@ class Plan:
         """Y^T maps (adjoint synthesis: analysis sums with unit weights)."""
         return self._run(_lib.sht_execute, ALM2MAP_ADJOINT, maps, self.alm_shape, stream, out)
 
+    def adjoint_analysis(self, alm, stream=None, out=None):
+        """W Y a: synthesis with every ring multiplied by its weight (the adjoint of map2alm)."""
+        return self._run(_lib.sht_execute, MAP2ALM_ADJOINT, alm, self.map_shape, stream, out)
+
     def alm2map_grad(self, grad_maps, stream=None, out=None):
         """dL/d(Re a) + i dL/d(Im a) of a real loss L from dL/dmap (fac_m Y^T g)."""
         return self._run(_lib.sht_execute, ALM2MAP_GRAD, grad_maps, self.alm_shape, stream, out)
@@ -241,8 +245,9 @@ class Plan:
     def legendre_anal(self, phases, stream=None):
         return self._run(_lib.sht_legendre, MAP2ALM, phases, self.alm_shape, stream)
 
-    def ring_synth(self, phases, stream=None):
-        return self._run(_lib.sht_ring_fft, ALM2MAP, phases, self.map_shape, stream)
+    def ring_synth(self, phases, weights: bool = False, stream=None):
+        d = MAP2ALM_ADJOINT if weights else ALM2MAP
+        return self._run(_lib.sht_ring_fft, d, phases, self.map_shape, stream)
 
     def ring_anal(self, maps, weights: bool = True, stream=None):
         d = MAP2ALM if weights else ALM2MAP_ADJOINT

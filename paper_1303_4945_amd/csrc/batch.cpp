@@ -20,7 +20,7 @@ namespace {
 
 void batch_free(Batch *b)
 {
-    for (int d = 0; d < 4; ++d)
+    for (int d = 0; d < NUM_DIRECTIONS; ++d)
         if (b->graph[d]) (void)hipGraphExecDestroy(b->graph[d]);
     dev_free(b->d_views);
     dev_free(b->d_syn);
@@ -77,14 +77,16 @@ int batch_enqueue(Batch &b, int direction, const double *const *in, double *cons
     std::memset(&ptrs, 0, sizeof(ptrs));
     const int np = (int)b.plans.size();
     int rc;
-    if (direction == SHT_ALM2MAP) {
+    if (synth_direction(direction)) {
         for (int i = 0; i < np; ++i) {
             ptrs.in[i] = in[i];
             ptrs.out[i] = b.plans[i]->d_phase;
         }
         if ((rc = launch_legendre_synth_batch(b, ptrs, s))) return rc;
         for (int i = 0; i < np; ++i)
-            if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i], s))) return rc;
+            if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i],
+                                        direction == SHT_MAP2ALM_ADJOINT, s)))
+                return rc;
     } else {
         for (int i = 0; i < np; ++i)
             if ((rc = launch_ring_anal(*b.plans[i], in[i], b.plans[i]->d_phase, direction == SHT_MAP2ALM, s)))

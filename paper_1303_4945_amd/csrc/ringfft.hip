@@ -734,7 +734,7 @@ __device__ __forceinline__ SpecRead<MODE> ring_transform(double2 *buf, const Fft
 template <int MODE, bool POW2>
 __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__restrict__ rowlist,
                                                     const double *__restrict__ phase,
-                                                    double *__restrict__ map)
+                                                    double *__restrict__ map, int use_weights)
 {
     extern __shared__ double2 buf[];
     const FftRow row = fv.rows[rowlist[blockIdx.x]];
@@ -743,6 +743,9 @@ __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__re
     const int N = row.nphi;
     const int64_t rowF = (int64_t)tc * fv.nrings;
     const double2 *Fa = reinterpret_cast<const double2 *>(phase) + (rowF + row.ya) * (fv.mmax + 1);
+    // adjoint of analysis: each ring times its weight
+    const double wa = use_weights ? fv.weight[row.ya] : 1.0;
+    const double wb = (use_weights && row.yb >= 0) ? fv.weight[row.yb] : 1.0;
     const int mva = min(fv.mvalid[row.ya], fv.mmax);
     double *mp = map + (int64_t)tc * fv.npix;
 
@@ -762,8 +765,8 @@ __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__re
         const SpecRead<MODE> out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
         for (int x = threadIdx.x; x < N; x += blockDim.x) {
             const double2 z = out(x);
-            mp[fv.ofs[row.ya] + (int64_t)x * fv.stride] = z.x;
-            if (row.yb >= 0) mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] = z.y;
+            mp[fv.ofs[row.ya] + (int64_t)x * fv.stride] = wa * z.x;
+            if (row.yb >= 0) mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] = wb * z.y;
         }
     } else {
         // even N = 2h: Z_k = X_k (1 + i w^k) + conj(X_{h-k}) (1 - i w^k), w = e^{2 pi i/N}
@@ -779,8 +782,8 @@ __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__re
         const SpecRead<MODE> out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
         for (int n = threadIdx.x; n < h; n += blockDim.x) {
             const double2 z = out(n);
-            mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride] = z.x;
-            mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride] = z.y;
+            mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride] = wa * z.x;
+            mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride] = wa * z.y;
         }
     }
 }
@@ -1474,11 +1477,11 @@ static int prepare_groups(const FftDev &D)
 
 template <int MODE, bool POW2>
 static int launch_group_synth(const FftView &v, const FftGroup &gr, const int *rows,
-                              const double *phase, double *map, int ntc, hipStream_t s)
+                              const double *phase, double *map, int ntc, int usew, hipStream_t s)
 {
     const size_t lds = (size_t)lds_padded(gr.lds_complex) * sizeof(double2);
     hipLaunchKernelGGL((k_ring_synth<MODE, POW2>), dim3((unsigned)gr.rows.size(), (unsigned)ntc),
-                       dim3(threads_for(gr)), lds, s, v, rows, phase, map);
+                       dim3(threads_for(gr)), lds, s, v, rows, phase, map, usew);
     return SHT_OK;
 }
 
@@ -1492,21 +1495,22 @@ static int launch_group_anal(const FftView &v, const FftGroup &gr, const int *ro
     return SHT_OK;
 }
 
-int launch_ring_synth(const Plan &p, const double *phase, double *map, hipStream_t s)
+int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_weights, hipStream_t s)
 {
     const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
     const FftView v = view_of(p, *D);
     const int ntc = p.ntrans * p.ncomp;
+    const int usew = use_weights ? 1 : 0;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
         int rc;
         // split Bluestein always has a power-of-two inner length
-        if (gr.mode == KMODE_SPLIT) rc = launch_group_synth<KMODE_SPLIT, true>(v, gr, rows, phase, map, ntc, s);
-        else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_synth<KMODE_RADER, true>(v, gr, rows, phase, map, ntc, s);
-        else if (gr.mode == KMODE_RADER) rc = launch_group_synth<KMODE_RADER, false>(v, gr, rows, phase, map, ntc, s);
-        else if (gr.pow2) rc = launch_group_synth<KMODE_LDS, true>(v, gr, rows, phase, map, ntc, s);
-        else rc = launch_group_synth<KMODE_LDS, false>(v, gr, rows, phase, map, ntc, s);
+        if (gr.mode == KMODE_SPLIT) rc = launch_group_synth<KMODE_SPLIT, true>(v, gr, rows, phase, map, ntc, usew, s);
+        else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_synth<KMODE_RADER, true>(v, gr, rows, phase, map, ntc, usew, s);
+        else if (gr.mode == KMODE_RADER) rc = launch_group_synth<KMODE_RADER, false>(v, gr, rows, phase, map, ntc, usew, s);
+        else if (gr.pow2) rc = launch_group_synth<KMODE_LDS, true>(v, gr, rows, phase, map, ntc, usew, s);
+        else rc = launch_group_synth<KMODE_LDS, false>(v, gr, rows, phase, map, ntc, usew, s);
         if (rc) return rc;
     }
     return check_hip(hipGetLastError(), "ring synthesis launch");

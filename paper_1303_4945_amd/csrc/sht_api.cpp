@@ -687,21 +687,20 @@ static bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb)
 int check_exec_args(const Plan *p, int direction, const void *in, const void *out, bool stage_fft,
                     bool stage_leg)
 {
-    if (direction != SHT_ALM2MAP && direction != SHT_MAP2ALM && direction != SHT_ALM2MAP_ADJOINT &&
-        direction != SHT_ALM2MAP_GRAD) {
+    if (direction < 0 || direction >= NUM_DIRECTIONS) {
         set_error("unknown direction %d", direction);
         return SHT_EINVAL;
     }
     if (!in || !out) { set_error("in and out must be device pointers"); return SHT_EINVAL; }
-    if (direction == SHT_MAP2ALM && !p->geom.has_weight && !stage_leg) {
-        set_error("geometry has no ring weights: analysis unavailable (use the adjoint)");
+    if ((direction == SHT_MAP2ALM || direction == SHT_MAP2ALM_ADJOINT) && !p->geom.has_weight && !stage_leg) {
+        set_error("geometry has no ring weights: analysis and its adjoint unavailable");
         return SHT_EINVAL;
     }
     const size_t alm_b = (size_t)p->ntrans * p->ncomp * p->nalm * 16;
     const size_t map_b = (size_t)p->ntrans * p->ncomp * p->geom.npix * 8;
     const size_t ph_b = (size_t)p->phase_elems * 16;
     size_t in_b, out_b;
-    if (direction == SHT_ALM2MAP) {
+    if (synth_direction(direction)) {
         in_b = stage_fft ? ph_b : alm_b;
         out_b = stage_leg ? ph_b : map_b;
     } else {
@@ -800,9 +799,9 @@ int sht_execute(sht_plan *h, int direction, const double *in, double *out, void 
     int rc = check_exec_args(p, direction, in, out, false, false);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (direction == SHT_ALM2MAP) {
+    if (synth_direction(direction)) {
         if ((rc = launch_legendre_synth(*p, in, p->d_phase, s))) return rc;
-        if ((rc = launch_ring_synth(*p, p->d_phase, out, s))) return rc;
+        if ((rc = launch_ring_synth(*p, p->d_phase, out, direction == SHT_MAP2ALM_ADJOINT, s))) return rc;
     } else {
         if ((rc = launch_ring_anal(*p, in, p->d_phase, direction == SHT_MAP2ALM, s))) return rc;
         if ((rc = launch_legendre_anal(*p, p->d_phase, out, direction == SHT_ALM2MAP_GRAD, s))) return rc;
@@ -817,7 +816,7 @@ int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, false, true);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (direction == SHT_ALM2MAP) rc = launch_legendre_synth(*p, in, out, s);
+    if (synth_direction(direction)) rc = launch_legendre_synth(*p, in, out, s);
     else rc = launch_legendre_anal(*p, in, out, direction == SHT_ALM2MAP_GRAD, s);
     if (rc) return rc;
     return finish_launch("sht_legendre");
@@ -830,7 +829,7 @@ int sht_ring_fft(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, true, false);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (direction == SHT_ALM2MAP) rc = launch_ring_synth(*p, in, out, s);
+    if (synth_direction(direction)) rc = launch_ring_synth(*p, in, out, direction == SHT_MAP2ALM_ADJOINT, s);
     else rc = launch_ring_anal(*p, in, out, direction == SHT_MAP2ALM, s);
     if (rc) return rc;
     return finish_launch("sht_ring_fft");
@@ -840,7 +839,7 @@ int sht_plan_flops(const sht_plan *h, int direction, double *flops, double *hbm_
 {
     Plan *p = as_plan(const_cast<sht_plan *>(h));
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
-    if (flops) *flops = direction == SHT_ALM2MAP ? p->flops_synth : p->flops_anal;
+    if (flops) *flops = synth_direction(direction) ? p->flops_synth : p->flops_anal;
     if (hbm_bytes) *hbm_bytes = p->hbm_bytes;
     return SHT_OK;
 }

@@ -144,6 +144,11 @@ constexpr int MAX_BATCH_PLANS = 64;
 
 // Legendre-step operands of the plans of a batch, passed by value to the
 // persistent kernels (so that a captured graph holds them as parameters).
+// directions of sht_execute (SHT_ALM2MAP .. SHT_MAP2ALM_ADJOINT); the two
+// that go from a_lm to maps run the synthesis kernels
+constexpr int NUM_DIRECTIONS = 5;
+inline bool synth_direction(int d) { return d == 0 || d == 4; }
+
 struct BatchPtrs {
     const double *in[MAX_BATCH_PLANS];
     double *out[MAX_BATCH_PLANS];
@@ -159,9 +164,9 @@ struct Batch {
     BatchAnaItem *d_ana = nullptr;
     unsigned *d_counter = nullptr;
     // captured graphs, one per direction, keyed by the user pointers
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
-    std::vector<const void *> graph_key[4];
-    hipStream_t graph_stream[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t graph[NUM_DIRECTIONS] = {};
+    std::vector<const void *> graph_key[NUM_DIRECTIONS];
+    hipStream_t graph_stream[NUM_DIRECTIONS] = {};
 };
 
 LegView make_leg_view(const Plan &p);
@@ -180,7 +185,7 @@ int anal_ncb(int spin, int ntrans);
 // ring FFT (ringfft.hip)
 int fft_plan_build(Plan &p);
 void fft_plan_free(FftPlan &f);
-int launch_ring_synth(const Plan &p, const double *phase, double *map, hipStream_t s);
+int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_weights, hipStream_t s);
 int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights,
                      hipStream_t s);
 
