@@ -102,6 +102,28 @@ int sht_geom_gauss(int nrings, int64_t nphi, double phi0, sht_geom **out);
 /* HEALPix ring-scheme grid (4 nside - 1 rings, 12 nside^2 pixels), uniform
    weights 4 pi / Npix. */
 int sht_geom_healpix(int nside, sht_geom **out);
+
+/* Equidistant-cylindrical (ECP) grids (Sect. 4.4, "Extended support for ECP
+   grids"), nphi pixels per ring, north to south:
+     SHT_ECP_FEJER1: nrings rings at (n + 1/2) pi / nrings, n = 0 .. nrings-1;
+     SHT_ECP_FEJER2: nrings rings at n pi / (nrings + 1), n = 1 .. nrings;
+     SHT_ECP_CC:     nrings >= 2 rings at n pi / (nrings - 1), n = 0 .. nrings-1
+                     (both poles included).
+   Weights: Fejer's first and second rules and the Clenshaw-Curtis rule for
+   the integral over x = cos theta (exact for polynomials in x of degree
+   nrings - 1), each times 2 pi / nphi. */
+enum { SHT_ECP_FEJER1 = 0, SHT_ECP_FEJER2 = 1, SHT_ECP_CC = 2 };
+int sht_geom_ecp(int nrings, int64_t nphi, int kind, double phi0, sht_geom **out);
+
+/* Reduced Gauss-Legendre grid (Sect. 4.4, "Reduced Gauss-Legendre grid"): the
+   rings of sht_geom_gauss(nrings, ...), ring y with 2 m_y + 1 pixels rounded up
+   to the next integer whose prime factors are 2, 3 and 5 (at most nphi_max),
+   where m_y <= mmax is the largest m whose terms the polar criterion of
+   Eqs. 7-8 keeps at that ring for lmax and spin (threshold T = max(100,
+   lmax / 100), |cos theta| for both spin signs).  Weights w_GL * 2 pi / nphi_y.
+   Not exact for analysis, but accurate to the criterion's precision. */
+int sht_geom_reduced_gauss(int nrings, int64_t nphi_max, int lmax, int mmax, int spin, double phi0,
+                           sht_geom **out);
 /* Number of rings and of map pixels (max pixel index + 1). */
 int sht_geom_info(const sht_geom *g, int *nrings, int64_t *npix);
 /* Copy the ring tables out (any pointer may be NULL). */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsht.so")
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_EUNSUPPORTED, SHT_ESTATE = range(6)
 FP64, FP32_MFMA = 0, 1
 ALM2MAP, MAP2ALM, ALM2MAP_ADJOINT, ALM2MAP_GRAD, MAP2ALM_ADJOINT = 0, 1, 2, 3, 4
+ECP_FEJER1, ECP_FEJER2, ECP_CC = 0, 1, 2
 
 _STATUS_NAMES = {1: "SHT_EINVAL", 2: "SHT_ENOMEM", 3: "SHT_EDEVICE", 4: "SHT_EUNSUPPORTED",
                  5: "SHT_ESTATE"}
@@ -64,6 +65,10 @@ _sig("sht_geom_create", ctypes.c_int, ctypes.c_int, _dp, _i64p, _dp, _dp, _i64p,
 _sig("sht_geom_gauss", ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
      ctypes.POINTER(_vp))
 _sig("sht_geom_healpix", ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
+_sig("sht_geom_ecp", ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+     ctypes.POINTER(_vp))
+_sig("sht_geom_reduced_gauss", ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+     ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp))
 _sig("sht_geom_info", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64))
 _sig("sht_geom_rings", ctypes.c_int, _vp, _dp, _i64p, _dp, _dp, _i64p)
 _sig("sht_geom_destroy", None, _vp)
@@ -144,6 +149,22 @@ class Geometry:
     def healpix(cls, nside: int):
         h = _vp()
         _check(_lib.sht_geom_healpix(nside, ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def ecp(cls, nrings: int, nphi: int, kind: int = 2, phi0: float = 0.0):
+        """Equidistant rings with Fejer-1 (kind 0), Fejer-2 (1) or Clenshaw-Curtis (2) weights."""
+        h = _vp()
+        _check(_lib.sht_geom_ecp(nrings, nphi, kind, phi0, ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def reduced_gauss(cls, nrings: int, nphi_max: int, lmax: int, mmax: int | None = None,
+                      spin: int = 0, phi0: float = 0.0):
+        """Gauss-Legendre rings with pixel counts thinned by the polar criterion."""
+        h = _vp()
+        mmax = lmax if mmax is None else mmax
+        _check(_lib.sht_geom_reduced_gauss(nrings, nphi_max, lmax, mmax, spin, phi0, ctypes.byref(h)))
         return cls(h)
 
     def rings(self):

@@ -228,6 +228,97 @@ int sht_geom_gauss(int nrings, int64_t nphi, double phi0, sht_geom **out)
     return sht_geom_create(nrings, th.data(), np.data(), p0.data(), wt.data(), nullptr, 1, out);
 }
 
+// Weights of the rules of sht_geom_ecp on [-1, 1] in x = cos theta, from the
+// closed-form cosine and sine sums of the interpolatory rules (the sums that
+// Waldvogel's FFT method evaluates), in long double.
+static void ecp_rule(int n, int kind, std::vector<double> &th, std::vector<double> &w)
+{
+    const long double pi = 3.14159265358979323846264338327950288L;
+    th.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        long double t = 0.0L, s = 0.0L;
+        if (kind == SHT_ECP_FEJER1) {
+            t = pi * ((long double)k + 0.5L) / n;
+            long double sum = 0.0L;
+            for (int j = 1; j <= n / 2; ++j) sum += cosl(2.0L * j * t) / (4.0L * j * j - 1.0L);
+            s = (2.0L / n) * (1.0L - 2.0L * sum);
+        } else if (kind == SHT_ECP_FEJER2) {
+            t = pi * (long double)(k + 1) / (n + 1);
+            long double sum = 0.0L;
+            for (int j = 1; j <= (n + 1) / 2; ++j) sum += sinl((2.0L * j - 1.0L) * t) / (2.0L * j - 1.0L);
+            s = 4.0L * sinl(t) / (n + 1) * sum;
+        } else {
+            const int N = n - 1;
+            t = pi * (long double)k / N;
+            long double sum = 0.0L;
+            for (int j = 1; j <= N / 2; ++j) {
+                const long double b = (2 * j == N) ? 1.0L : 2.0L;
+                sum += b * cosl(2.0L * j * t) / (4.0L * j * j - 1.0L);
+            }
+            const long double c = (k == 0 || k == N) ? 1.0L : 2.0L;
+            s = c / N * (1.0L - sum);
+        }
+        th[k] = (double)t;
+        w[k] = (double)s;
+    }
+}
+
+int sht_geom_ecp(int nrings, int64_t nphi, int kind, double phi0, sht_geom **out)
+{
+    if (!out) { set_error("out is NULL"); return SHT_EINVAL; }
+    *out = nullptr;
+    if (kind != SHT_ECP_FEJER1 && kind != SHT_ECP_FEJER2 && kind != SHT_ECP_CC) {
+        set_error("unknown ECP kind %d", kind);
+        return SHT_EINVAL;
+    }
+    const int nmin = kind == SHT_ECP_CC ? 2 : 1;
+    if (nrings < nmin || nrings > 65536) { set_error("nrings %d outside [%d, 65536]", nrings, nmin); return SHT_EINVAL; }
+    if (nphi < 1) { set_error("nphi must be >= 1"); return SHT_EINVAL; }
+    std::vector<double> th, w;
+    ecp_rule(nrings, kind, th, w);
+    std::vector<int64_t> np(nrings, nphi);
+    std::vector<double> p0(nrings, phi0), wt(nrings);
+    for (int i = 0; i < nrings; ++i) wt[i] = w[i] * (2.0 * M_PI / (double)nphi);
+    return sht_geom_create(nrings, th.data(), np.data(), p0.data(), wt.data(), nullptr, 1, out);
+}
+
+static bool smooth235(int64_t n)
+{
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+int sht_geom_reduced_gauss(int nrings, int64_t nphi_max, int lmax, int mmax, int spin, double phi0,
+                           sht_geom **out)
+{
+    if (!out) { set_error("out is NULL"); return SHT_EINVAL; }
+    *out = nullptr;
+    if (nrings < 1 || nrings > 65536) { set_error("nrings %d outside [1, 65536]", nrings); return SHT_EINVAL; }
+    if (lmax < 0 || mmax < 0 || mmax > lmax || spin < 0 || spin > lmax) {
+        set_error("need 0 <= mmax <= lmax and 0 <= spin <= lmax");
+        return SHT_EINVAL;
+    }
+    if (nphi_max < 1) { set_error("nphi_max must be >= 1"); return SHT_EINVAL; }
+    std::vector<double> th, w;
+    gauss_legendre(nrings, th, w);
+    const double T = std::max(100.0, 0.01 * lmax), sp = (double)spin;
+    std::vector<int64_t> np(nrings);
+    std::vector<double> p0(nrings, phi0), wt(nrings);
+    for (int i = 0; i < nrings; ++i) {
+        const double c = fabs(cos(th[i])), st = sin(th[i]);
+        int mlim = mmax;
+        while (mlim > 0 && sqrt(std::max(0.0, (double)mlim * mlim + sp * sp - 2.0 * mlim * sp * c)) - lmax * st > T)
+            --mlim;
+        int64_t n = 2 * (int64_t)mlim + 1;
+        while (!smooth235(n)) ++n;
+        np[i] = std::min(n, nphi_max);
+        wt[i] = w[i] * (2.0 * M_PI / (double)np[i]);
+    }
+    return sht_geom_create(nrings, th.data(), np.data(), p0.data(), wt.data(), nullptr, 1, out);
+}
+
 int sht_geom_healpix(int nside, sht_geom **out)
 {
     if (!out) { set_error("out is NULL"); return SHT_EINVAL; }

@@ -128,6 +128,71 @@ def mixed_geometry(nphi_north, phi0: float = 0.0) -> Geometry:
     return Geometry(g.theta, nph, ph, weight, _packed_offsets(nph))
 
 
+ECP_FEJER1, ECP_FEJER2, ECP_CC = 0, 1, 2
+
+
+def ecp_rule(n: int, kind: int):
+    """Colatitudes (north to south) and weights on [-1, 1] in x = cos theta of
+    the equidistant rules: Fejer's first rule (theta = (k + 1/2) pi / n),
+    Fejer's second rule (theta = k pi / (n + 1), k = 1 .. n) and Clenshaw-Curtis
+    (theta = k pi / (n - 1), k = 0 .. n - 1), from their closed-form sums."""
+    if kind == ECP_FEJER1:
+        th = np.pi * (np.arange(n) + 0.5) / n
+        j = np.arange(1, n // 2 + 1)
+        w = (2.0 / n) * (1.0 - 2.0 * (np.cos(2.0 * np.outer(th, j)) / (4.0 * j * j - 1.0)).sum(axis=1))
+    elif kind == ECP_FEJER2:
+        th = np.pi * np.arange(1, n + 1) / (n + 1)
+        j = np.arange(1, (n + 1) // 2 + 1)
+        w = 4.0 * np.sin(th) / (n + 1) * (np.sin(np.outer(th, 2 * j - 1)) / (2 * j - 1)).sum(axis=1)
+    elif kind == ECP_CC:
+        N = n - 1
+        th = np.pi * np.arange(n) / N
+        j = np.arange(1, N // 2 + 1)
+        b = np.where(2 * j == N, 1.0, 2.0)
+        c = np.where((np.arange(n) == 0) | (np.arange(n) == N), 1.0, 2.0)
+        w = c / N * (1.0 - (b * np.cos(2.0 * np.outer(th, j)) / (4.0 * j * j - 1.0)).sum(axis=1))
+    else:
+        raise ValueError(kind)
+    return th, w
+
+
+def ecp_geometry(nrings: int, nphi: int, kind: int, phi0: float = 0.0) -> Geometry:
+    """Equidistant-cylindrical grid with the rule of `kind` (weights times 2 pi / nphi)."""
+    th, w = ecp_rule(nrings, kind)
+    nph = np.full(nrings, nphi, dtype=np.int64)
+    return Geometry(th, nph, np.full(nrings, float(phi0)), w * (2.0 * math.pi / nph),
+                    _packed_offsets(nph))
+
+
+def _smooth235(n: int) -> bool:
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def reduced_gauss_geometry(nrings: int, nphi_max: int, lmax: int, mmax: int, spin: int,
+                           phi0: float = 0.0) -> Geometry:
+    """Gauss-Legendre rings, ring y with 2 m_y + 1 pixels rounded up to the next
+    2,3,5-smooth number (at most nphi_max), m_y <= mmax the largest m whose terms
+    the polar criterion sqrt(m^2 + s^2 - 2 m s |cos t|) - lmax sin t <= T keeps,
+    T = max(100, lmax / 100)."""
+    g = gauss_geometry(nrings, 1, phi0)
+    wgl = g.weight / (2.0 * math.pi)
+    T = max(100.0, 0.01 * lmax)
+    nph = np.zeros(nrings, dtype=np.int64)
+    for y in range(nrings):
+        c, st = abs(math.cos(g.theta[y])), math.sin(g.theta[y])
+        m = mmax
+        while m > 0 and math.sqrt(max(0.0, m * m + spin * spin - 2.0 * m * spin * c)) - lmax * st > T:
+            m -= 1
+        n = 2 * m + 1
+        while not _smooth235(n):
+            n += 1
+        nph[y] = min(n, nphi_max)
+    return Geometry(g.theta, nph, g.phi0, wgl * (2.0 * math.pi / nph), _packed_offsets(nph))
+
+
 def healpix_geometry(nside: int) -> Geometry:
     """HEALPix ring-scheme geometry (pixel order within a ring as in HEALPix)."""
     nr = 4 * nside - 1
