@@ -27,15 +27,18 @@
  * Conventions (where the paper is silent, these are the readings used):
  *   - real fields: a_{l,-m} = (-1)^m conj(a_lm); the imaginary part of a_l0
  *     is ignored, and coefficients with l < |s| are ignored (set to zero);
- *   - spin 2 uses E/B input and Q/U maps with s_a_lm = -(E_lm + i s/|s| B_lm)
- *     for s = +-2, and Q + iU = sum 2_a_lm 2_Y_lm;
+ *   - spin s > 0 uses E/B input and Q/U maps with
+ *     +-s_a_lm = -(E_lm +- i B_lm) and Q + iU = sum s_a_lm s_Y_lm; since
+ *     -s_Y_lm = (-1)^(s+m) conj(s_Y_l,-m) (from Eq. 10 and the symmetries of
+ *     d^l), real Q and U give Q - iU = (-1)^s sum -s_a_lm -s_Y_lm, so the
+ *     analysis takes -s_a from Q - iU with the factor (-1)^s (1 for even s);
  *   - Eq. 2's weights w_y include the 2 pi / Nphi_y factor.
  *
  * Layouts (all double precision, complex numbers as (re, im) pairs):
  *   alm  [ntrans][ncomp][nalm][2], index(l,m) = m(2 lmax + 1 - m)/2 + l
  *   map  [ntrans][ncomp][...], pixel x of ring y at ofs[y] + x*stride
  *   phases F or G  [ntrans][ncomp][nrings][mmax+1][2]
- * ncomp is 1 for spin 0 and 2 for spin 2 (E,B resp. Q,U).
+ * ncomp is 1 for spin 0 and 2 for spin s > 0 (E,B resp. Q,U).
  */
 #include <math.h>
 #include <stdint.h>
@@ -270,8 +273,7 @@ int oracle_synthesis(int nrings, const double *theta, const int64_t *nphi,
                      const double *alm, double *map, int nsel, const int *sel,
                      double *F)
 {
-    if (lmax < 0 || mmax < 0 || mmax > lmax || !(spin == 0 || spin == 2) ||
-        spin > lmax || ntrans < 1 || nrings < 1)
+    if (lmax < 0 || mmax < 0 || mmax > lmax || spin < 0 || spin > lmax || ntrans < 1 || nrings < 1)
         return -1;
     const int ncomp = spin ? 2 : 1;
     const int64_t nalm = oracle_nalm(lmax, mmax);
@@ -316,15 +318,15 @@ int oracle_synthesis(int nrings, const double *theta, const int64_t *nphi,
                     ph[(size_t)t * (2 * mmax + 1) + (m + mmax)] = acc;
                 }
             } else {
-                /* Q + iU = sum_m sum_l 2_a_lm 2_lambda_lm e^{i m phi},
-                   2_a_lm = -(E_lm + i B_lm) */
-                lambda_column(lmax, m, 2, theta[y], fact, lam);
+                /* Q + iU = sum_m sum_l s_a_lm s_lambda_lm e^{i m phi},
+                   s_a_lm = -(E_lm + i B_lm) */
+                lambda_column(lmax, m, spin, theta[y], fact, lam);
                 for (int t = 0; t < ntrans; ++t) {
                     const double *aE = alm + ((size_t)t * 2 + 0) * nalm * 2;
                     const double *aB = alm + ((size_t)t * 2 + 1) * nalm * 2;
                     cld acc = { 0.0L, 0.0L };
                     int am = m < 0 ? -m : m;
-                    int lstart = am > 2 ? am : 2;
+                    int lstart = am > spin ? am : spin;
                     for (int l = lstart; l <= lmax; ++l) {
                         cld e = coef_real_field(aE, lmax, l, m);
                         cld b = coef_real_field(aB, lmax, l, m);
@@ -408,8 +410,9 @@ int oracle_synthesis(int nrings, const double *theta, const int64_t *nphi,
  * wgt: ring weights w_y (pass all ones for the adjoint synthesis Y^T).
  * G (optional) receives G^c_{m,y} = w_y sum_x p^c_xy e^{-i m phi} for each
  * map component c (all rings, the selected m only).
- * For spin 2: s_a_lm = sum_y sum_x w_y (Q + i s/|s| U) s_lambda_lm e^{-i m phi}
- * for s = +-2, E = -(2_a + -2_a)/2, B = i (2_a - -2_a)/2.
+ * For spin s > 0: s_a_lm = sum_y sum_x w_y (Q + iU) s_lambda_lm e^{-i m phi},
+ * -s_a_lm = (-1)^s sum_y sum_x w_y (Q - iU) -s_lambda_lm e^{-i m phi},
+ * E = -(s_a + -s_a)/2, B = i (s_a - -s_a)/2.
  */
 int oracle_analysis(int nrings, const double *theta, const int64_t *nphi,
                     const double *phi0, const double *wgt, const int64_t *ofs,
@@ -417,8 +420,7 @@ int oracle_analysis(int nrings, const double *theta, const int64_t *nphi,
                     const double *map, double *alm, int nsel, const int *msel,
                     double *G)
 {
-    if (lmax < 0 || mmax < 0 || mmax > lmax || !(spin == 0 || spin == 2) ||
-        spin > lmax || ntrans < 1 || nrings < 1)
+    if (lmax < 0 || mmax < 0 || mmax > lmax || spin < 0 || spin > lmax || ntrans < 1 || nrings < 1)
         return -1;
     const int ncomp = spin ? 2 : 1;
     const int64_t nalm = oracle_nalm(lmax, mmax);
@@ -499,14 +501,17 @@ int oracle_analysis(int nrings, const double *theta, const int64_t *nphi,
                 }
             free(acc);
         } else {
-            /* sp[t][l] = 2_a_lm, sm[t][l] = -2_a_lm */
+            /* sp[t][l] = s_a_lm, sm[t][l] = -s_a_lm */
             cld *sp = (cld *)calloc((size_t)ntrans * (lmax + 1), sizeof(cld));
             cld *sm = (cld *)calloc((size_t)ntrans * (lmax + 1), sizeof(cld));
-            int lstart = m > 2 ? m : 2;
+            int lstart = m > spin ? m : spin;
+            const ld sfac = (spin & 1) ? -1.0L : 1.0L;   /* (-1)^s for the -s part */
             for (int sg = -1; sg <= 1; sg += 2) {
                 cld *dst = sg > 0 ? sp : sm;
                 for (int y = 0; y < nrings; ++y) {
-                    lambda_column(lmax, m, 2 * sg, theta[y], fact, lam);
+                    lambda_column(lmax, m, spin * sg, theta[y], fact, lam);
+                    if (sg < 0)
+                        for (int l = 0; l <= lmax; ++l) lam[l] = (double)(sfac * lam[l]);
                     for (int t = 0; t < ntrans; ++t) {
                         cld q = g[((size_t)t * 2 + 0) * nrings + y];
                         cld u = g[((size_t)t * 2 + 1) * nrings + y];
@@ -523,7 +528,7 @@ int oracle_analysis(int nrings, const double *theta, const int64_t *nphi,
                 for (int l = m; l <= lmax; ++l) {
                     double *oE = alm + (((size_t)t * 2 + 0) * nalm + oracle_alm_index(lmax, l, m)) * 2;
                     double *oB = alm + (((size_t)t * 2 + 1) * nalm + oracle_alm_index(lmax, l, m)) * 2;
-                    if (l < 2) { oE[0] = oE[1] = oB[0] = oB[1] = 0.0; continue; }
+                    if (l < spin) { oE[0] = oE[1] = oB[0] = oB[1] = 0.0; continue; }
                     cld p = sp[(size_t)t * (lmax + 1) + l], q = sm[(size_t)t * (lmax + 1) + l];
                     /* E = -(p + q)/2 ; B = i (p - q)/2 */
                     ld Ere = -0.5L * (p.re + q.re), Eim = -0.5L * (p.im + q.im);

@@ -204,13 +204,54 @@ def test_recursion_against_explicit_sum():
     """Every degree from the Eq. 11 recursion equals Wigner's full explicit sum
     (the oracle only uses the sum at the lowest degree)."""
     beta = 0.83
-    for s in (0, 2, -2):
+    for s in (0, 2, -2, 1, -1, 3, -3):
         for m in (-5, -2, 0, 1, 4):
             lam = oracle.lam(24, m, s, beta)
             for l in range(max(abs(m), abs(s)), 25):
                 d = _mp_d_explicit(l, -m, s, beta)
                 ref = (-1) ** m * math.sqrt((2 * l + 1) / FOURPI) * d
                 assert abs(lam[l] - ref) < 1e-13, (s, m, l)
+
+
+def test_recursion_against_explicit_sum_spin37():
+    """The spin the paper's tests use: s = 37 at degrees up to 60."""
+    beta = 1.31
+    for s in (37, -37):
+        for m in (0, 5, -20, 40):
+            lam = oracle.lam(60, m, s, beta)
+            for l in range(max(abs(m), abs(s)), 61, 7):
+                d = _mp_d_explicit(l, -m, s, beta)
+                ref = (-1) ** m * math.sqrt((2 * l + 1) / FOURPI) * d
+                assert abs(lam[l] - ref) < 1e-13, (s, m, l)
+
+
+@pytest.mark.parametrize("s", [1, 3, 37])
+def test_addition_theorem_any_spin(s):
+    """sum_m |s_lambda_lm|^2 = (2l+1)/(4 pi) for every l >= s."""
+    lmax = 160
+    for theta in (0.05, 1.0, 2.5):
+        for sg in (s, -s):
+            tot = np.zeros(lmax + 1)
+            for m in range(-lmax, lmax + 1):
+                tot += oracle.lam(lmax, m, sg, theta) ** 2
+            ls = np.arange(s, lmax + 1)
+            ref = (2 * ls + 1) / FOURPI
+            assert np.max(np.abs(tot[s:] - ref) / ref) < 1e-13
+
+
+def test_parity_relation_odd_spin():
+    """s_lambda_lm(pi - theta) = (-1)^(l+m) (-s)_lambda_lm(theta) for odd s, and
+    -s_lambda_lm = (-1)^(s+m) s_lambda_l,-m (the relation behind the (-1)^s of
+    the real-field Q - iU)."""
+    lmax, theta = 80, 0.7
+    for s in (1, 3, -3):
+        for m in (-6, 0, 5, 33):
+            a = oracle.lam(lmax, m, s, math.pi - theta)
+            b = oracle.lam(lmax, m, -s, theta)
+            sign = (-1.0) ** (np.arange(lmax + 1) + m)
+            assert np.max(np.abs(a - sign * b)) < 1e-13
+            c = oracle.lam(lmax, -m, s, theta)
+            assert np.max(np.abs(b - (-1.0) ** (s + m) * c)) < 1e-13
 
 
 def test_wigner_d_orthogonality_and_limits():
@@ -334,7 +375,7 @@ def test_phases_against_numpy_fft():
         assert np.max(np.abs(fw - gg)) < 1e-12
 
 
-@pytest.mark.parametrize("spin", [0, 2])
+@pytest.mark.parametrize("spin", [0, 1, 2, 3, 4])
 def test_gauss_round_trip_small(spin):
     lmax = 31
     g = si.gauss_geometry(lmax + 1, 2 * lmax + 1, phi0=0.25)
@@ -353,7 +394,7 @@ def test_gauss_round_trip_gl127():
     assert err < 1e-12, err
 
 
-@pytest.mark.parametrize("spin", [0, 2])
+@pytest.mark.parametrize("spin", [0, 1, 2, 3])
 def test_adjoint_dot_product(spin):
     """<Y a, g> = sum_lm fac_m Re(conj(a_lm) (Y^T g)_lm), fac_0 = 1, fac_m>0 = 2,
     on a HEALPix grid (no quadrature exactness involved)."""
