@@ -12,15 +12,17 @@
  *                                 every weight equal to one (Y^T).
  *
  * Both are split into a Legendre step (Eqs. 4, 5: the phases F_{m,y}, G_{m,y})
- * and per-ring real FFTs (Eqs. 3, 6).  Spin 0 and spin 2 are supported
+ * and per-ring real FFTs (Eqs. 3, 6).  Every spin 0 <= s <= lmax is supported
  * (Sect. 4.1); several transforms of identical type run together (Sect. 3.2).
  *
  * Conventions
  *   - real fields: only m >= 0 is stored, a_{l,-m} = (-1)^m conj(a_lm);
  *     Im(a_l0) is ignored on input and returned as 0; coefficients with
  *     l < |spin| are ignored on input and returned as 0;
- *   - spin 2 takes E/B coefficients and Q/U maps with
- *     -+2 a_lm = -(E_lm +- i B_lm) and Q +- iU = sum_lm +-2 a_lm +-2 Y_lm;
+ *   - spin s > 0 takes E/B coefficients and Q/U maps with
+ *     +-s a_lm = -(E_lm +- i B_lm), Q + iU = sum_lm s a_lm s Y_lm and
+ *     Q - iU = (-1)^s sum_lm -s a_lm -s Y_lm (what real Q, U imply, since
+ *     -s Y_lm = (-1)^(s+m) conj(s Y_l,-m)); for s = 2 the HEALPix convention;
  *   - the ring weights w_y of Eq. 2 include the 2 pi / Nphi_y factor
  *     (Gauss-Legendre: w_GL * 2 pi / Nphi; HEALPix: 4 pi / Npix).
  *
@@ -30,7 +32,7 @@
  *   maps   double[ntrans][ncomp][npix], pixel x of ring y at ofs[y] + x*stride
  *   phases double[ntrans][ncomp][nrings][mmax + 1][2]  (F for synthesis, G for
  *          analysis; ring index = the geometry's ring order)
- *   ncomp is 1 for spin 0 and 2 for spin 2 (E,B resp. Q,U).
+ *   ncomp is 1 for spin 0 and 2 for spin s > 0 (E,B resp. Q,U).
  *
  * Memory and ownership
  *   - every data pointer passed to sht_execute / sht_legendre / sht_ring_fft
@@ -137,8 +139,8 @@ int64_t sht_nalm(int lmax, int mmax);            /* number of stored a_lm */
 
 /* ---- plans ---- */
 
-/* A plan binds a geometry (copied), band limits lmax >= mmax >= 0, spin (0 or 2;
-   spin <= lmax), the number of simultaneous transforms ntrans >= 1 (Sect. 3.2)
+/* A plan binds a geometry (copied), band limits lmax >= mmax >= 0, a spin
+   0 <= spin <= lmax, the number of simultaneous transforms ntrans >= 1 (Sect. 3.2)
    and the arithmetic of the Legendre step (SHT_FP64, or SHT_FP32_MFMA: FP64
    recursion, FP32 matrix-core products with FP64 carry).  Uses the current
    HIP device. */

@@ -17,12 +17,14 @@
 //
 // Synthesis (Eq. 4), per (m, slot tile):
 //   C[slot][col] += sum_k Lambda[slot][k] Coef[k][col]
-// k runs over degrees (spin 0) or (degree, W/X) pairs (spin 2) of one parity
-// class, col over (transform, component, re/im).  With
-// lambda(pi-t) = (-1)^(l+m) lambda(t) (spin 0), resp. W(pi-t) = (-1)^(l+m) W(t),
-// X(pi-t) = -(-1)^(l+m) X(t) for W, X = (2lambda +- -2lambda)/2 (spin 2), two
-// class accumulators A0, A1 give both rings: t: A0 + A1, pi - t: A0 - A1.
-// Spin-2 column maps (HEALPix convention -+2 a = -(E +- iB)):
+// k runs over degrees (spin 0) or (degree, W/X) pairs (spin s > 0) of one
+// parity class, col over (transform, component, re/im).  For spin s the -s
+// chain carries the factor sigma = (-1)^s (real Q, U: Q - iU = sigma sum -s_a
+// -s_Y), W, X = (s_lambda +- sigma -s_lambda)/2, and then
+// W(pi-t) = sigma (-1)^(l+m) W(t), X(pi-t) = -sigma (-1)^(l+m) X(t) (spin 0:
+// lambda(pi-t) = (-1)^(l+m) lambda(t), sigma = 1), so two class accumulators
+// A0, A1 give both rings: t: A0 + A1, pi - t: sigma (A0 - A1).
+// Column maps (+-s a = -(E +- iB), the HEALPix convention for s = 2):
 //   Q_re = -E_re W + B_im X,  Q_im = -E_im W - B_re X,
 //   U_re = -B_re W - E_im X,  U_im = -B_im W + E_re X.
 //
@@ -317,7 +319,8 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
     if (it.m < 0) return;
     const int m = it.m, tile = it.tile, t0 = it.t0;
     const int lmax = v.lmax;
-    const int l0 = m > SPIN ? m : SPIN;
+    const int l0 = (SPIN && v.spin > m) ? v.spin : m;
+    const double ssign = (SPIN && (v.spin & 1)) ? -1.0 : 1.0;   // sigma = (-1)^s of the mirror ring
     const int lstart = l0 - ((l0 + m) & 1);
     const double4 *coef = v.coef + v.coef_ofs[m];
     const double *flm = v.fl + v.coef_ofs[m];
@@ -555,7 +558,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
                 const int yn = eyn[sb][r], ys = eys[sb][r];
                 const int64_t rowbase = ((int64_t)t * NCOMP + comp) * v.nrings;
                 if (yn >= 0) phase[((rowbase + yn) * (v.mmax + 1) + m) * 2 + reim] = c0 + c1;
-                if (ys >= 0) phase[((rowbase + ys) * (v.mmax + 1) + m) * 2 + reim] = c0 - c1;
+                if (ys >= 0) phase[((rowbase + ys) * (v.mmax + 1) + m) * 2 + reim] = ssign * (c0 - c1);
             }
 }
 
@@ -671,7 +674,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     const int wave = tid >> 6, lane = tid & 63;
     const int i16 = lane & 15, kk = lane >> 4;
     const int lmax = v.lmax;
-    const int l0 = m > SPIN ? m : SPIN;
+    const int l0 = (SPIN && v.spin > m) ? v.spin : m;
+    const double ssign = (SPIN && (v.spin & 1)) ? -1.0 : 1.0;   // sigma = (-1)^s of the mirror ring
     const int lstart = l0 - ((l0 + m) & 1);
     const double4 *coef = v.coef + v.coef_ofs[m];
     const double *flm = v.fl + v.coef_ofs[m];
@@ -701,14 +705,17 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     // invalid ones go to the start of alm instead)
     double *const obase = alm + (((int64_t)t0 * NCOMP + tc0) * v.nalm + mbase) * 2 + oreim;
 
-    // degrees below l0 (spin 2 with m < 2) are zero by convention
-    for (int e = tid; e < 2 * NCOMP * (NCOL / CPJ) * 2; e += NT) {
-        const int l = m + (e & 1);
-        const int rest = e >> 1;
-        const int reim = rest & 1, tc = rest >> 1;
-        const int t = t0 + tc / NCOMP, comp = tc % NCOMP;
-        if (l < l0 && t < v.ntrans)
-            alm[(((int64_t)t * NCOMP + comp) * v.nalm + mbase + l) * 2 + reim] = 0.0;
+    // degrees m .. l0-1 (spin s > m) are zero by convention
+    {
+        const int nz = l0 - m;
+        for (int e = tid; e < nz * 2 * NCOMP * (NCOL / CPJ); e += NT) {
+            const int l = m + e % nz;
+            const int rest = e / nz;
+            const int reim = rest & 1, tc = rest >> 1;
+            const int t = t0 + tc / NCOMP, comp = tc % NCOMP;
+            if (t < v.ntrans)
+                alm[(((int64_t)t * NCOMP + comp) * v.nalm + mbase + l) * 2 + reim] = 0.0;
+        }
     }
 
     int ntiles_act = 0;
@@ -770,7 +777,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                     const double gn0 = phase[((rowbase + (yn >= 0 ? yn : 0)) * (v.mmax + 1) + m) * 2 + reim];
                     const double gs0 = phase[((rowbase + (ys >= 0 ? ys : 0)) * (v.mmax + 1) + m) * 2 + reim];
                     const double gn = (tok && yn >= 0) ? gn0 : 0.0;
-                    const double gs = (tok && ys >= 0) ? gs0 : 0.0;
+                    const double gs = (tok && ys >= 0) ? ssign * gs0 : 0.0;
                     const double sg = SPIN ? -1.0 : 1.0;
                     gw[i][0][ks][cb] = (T)(sg * (gn + gs));
                     gw[i][1][ks][cb] = (T)(sg * (gn - gs));

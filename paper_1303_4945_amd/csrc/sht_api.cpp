@@ -547,6 +547,9 @@ static void build_coef(Plan &p, std::vector<double4> &coef, std::vector<double> 
 //   m <  s:  d^s_{-m, s}  = sqrt(C(2s, s+m)) cos(t/2)^(s-m) sin(t/2)^(s+m)
 //            d^s_{-m,-s}  = (-1)^(s-m) sqrt(C(2s, s+m)) cos(t/2)^(s+m) sin(t/2)^(s-m)
 // times (-1)^m sqrt((2 l0 + 1)/4pi) (Eq. 10).  K is kept as mantissa/exponent.
+// The -s chain carries an extra (-1)^s, so that W = (s_lambda + (-1)^s
+// -s_lambda)/2 and X = (s_lambda - (-1)^s -s_lambda)/2 give Q and U with the
+// same column maps for every spin (real Q, U: Q - iU = (-1)^s sum -s_a -s_Y).
 static void build_start(Plan &p, std::vector<StartCoef> &st)
 {
     const int s = p.spin;
@@ -566,6 +569,7 @@ static void build_start(Plan &p, std::vector<StartCoef> &st)
                 if (sig > 0) { p_ = s - m; q_ = s + m; }
                 else { p_ = s + m; q_ = s - m; if ((s - m) & 1) sign = -sign; }
             }
+            if (ch == 1 && (s & 1)) sign = -sign;
             // C(2 l0, top) as mantissa/exponent, via a product of ratios
             long double mant = 1.0L;
             long e = 0;
@@ -603,8 +607,8 @@ static void build_start(Plan &p, std::vector<StartCoef> &st)
 }
 
 // Algorithmic work of the Legendre step (see sht.h): per kept (m, slot, l)
-// triple the recursion (4 flops for spin 0: two FMAs; 8 for spin 2: two
-// chains) plus per transform and ring of the slot 4 (spin 0) / 16 (spin 2)
+// triple the recursion (4 flops for spin 0: two FMAs; 8 for spin s > 0: two
+// chains) plus per transform and ring of the slot 4 (spin 0) / 16 (spin s > 0)
 // flops of products; HBM: a_lm + 2 x phases + maps.
 static void count_work(Plan &p)
 {
@@ -829,7 +833,6 @@ int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans,
     if (lmax < 0 || lmax > 16383) { set_error("lmax %d outside [0, 16383]", lmax); return SHT_EINVAL; }
     if (mmax < 0 || mmax > lmax) { set_error("mmax %d outside [0, lmax=%d]", mmax, lmax); return SHT_EINVAL; }
     if (spin < 0) { set_error("spin must be >= 0"); return SHT_EINVAL; }
-    if (spin != 0 && spin != 2) { set_error("spin %d not supported (0 or 2)", spin); return SHT_EUNSUPPORTED; }
     if (spin > lmax) { set_error("spin %d exceeds lmax %d", spin, lmax); return SHT_EINVAL; }
     if (ntrans < 1 || ntrans > 4096) { set_error("ntrans %d outside [1, 4096]", ntrans); return SHT_EINVAL; }
     if (precision != SHT_FP64 && precision != SHT_FP32_MFMA) { set_error("unknown precision %d", precision); return SHT_EINVAL; }

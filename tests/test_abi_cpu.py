@@ -85,14 +85,12 @@ def test_plan_argument_validation_before_device():
     sht = _sht()
     g = sht.Geometry.gauss(8, 17)
     cases = [dict(lmax=-1), dict(lmax=7, mmax=9), dict(lmax=7, ntrans=0),
-             dict(lmax=1, spin=2), dict(lmax=7, precision=7), dict(lmax=7, rescale_bits=10)]
+             dict(lmax=1, spin=2), dict(lmax=7, spin=-1), dict(lmax=3, spin=4),
+             dict(lmax=7, precision=7), dict(lmax=7, rescale_bits=10)]
     for kw in cases:
         with pytest.raises(sht.ShtError) as e:
             sht.Plan(g, **kw)
         assert e.value.status == sht.SHT_EINVAL, kw
-    with pytest.raises(sht.ShtError) as e:
-        sht.Plan(g, 7, spin=1)
-    assert e.value.status == sht.SHT_EUNSUPPORTED
 
 
 def test_invalid_handles():
