@@ -136,3 +136,33 @@ def analysis(geom, lmax: int, mmax: int, spin: int, maps: np.ndarray, weight=Non
 def adjoint_synthesis(geom, lmax: int, mmax: int, spin: int, maps: np.ndarray, ms=None):
     """Y^T applied to maps: the analysis sums with all weights equal to one."""
     return analysis(geom, lmax, mmax, spin, maps, weight=1.0, ms=ms)
+
+
+def _degrees(lmax: int, mmax: int) -> np.ndarray:
+    """l of every stored coefficient, m-major order (m = 0 .. mmax, l = m .. lmax)."""
+    return np.concatenate([np.arange(m, lmax + 1) for m in range(mmax + 1)]).astype(np.float64)
+
+
+def deriv_synthesis(geom, lmax: int, mmax: int, alm: np.ndarray, rings=None):
+    """Maps of the first derivatives of a real scalar field (Sect. 4.3).
+
+    alm float64 [ntrans][1][nalm][2] (spin 0) -> [ntrans][2][npix] holding
+    df/dtheta and df/(sin theta dphi).  Following the paper's remark that this
+    is a spin-1 transform: the spin-raising operator maps Y_lm to
+    sqrt(l (l + 1)) times the spin-1 harmonic, and with the convention
+    Q + iU = sum 1_a 1_Y, 1_a = -(E + iB), the spin-1 synthesis of
+    E = sqrt(l (l + 1)) a, B = 0 is Q = df/dtheta, U = df/(sin theta dphi).
+    """
+    alm = np.asarray(alm, dtype=np.float64)
+    k = np.sqrt(_degrees(lmax, mmax) * (_degrees(lmax, mmax) + 1.0))
+    e = np.zeros((alm.shape[0], 2) + alm.shape[2:])
+    e[:, 0] = alm[:, 0] * k[:, None]
+    return synthesis(geom, lmax, mmax, 1, e, rings=rings)
+
+
+def deriv_adjoint(geom, lmax: int, mmax: int, maps: np.ndarray, ms=None):
+    """Adjoint of deriv_synthesis: maps [ntrans][2][npix] -> [ntrans][1][nalm][2],
+    sqrt(l (l + 1)) times the E part of the spin-1 Y^T."""
+    eb = adjoint_synthesis(geom, lmax, mmax, 1, maps, ms=ms)
+    k = np.sqrt(_degrees(lmax, mmax) * (_degrees(lmax, mmax) + 1.0))
+    return eb[:, :1] * k[None, None, :, None]

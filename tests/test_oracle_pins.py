@@ -445,3 +445,80 @@ def test_ignored_inputs():
             b[:, :, ls < 2, :] = 3.0
         assert np.array_equal(oracle.synthesis(g, lmax, lmax, spin, a),
                               oracle.synthesis(g, lmax, lmax, spin, b))
+
+
+# ---------------------------------------------------------------- first derivatives (Sect. 4.3)
+
+def _rings_geometry(theta, nphi, phi0):
+    theta = np.asarray(theta, dtype=np.float64)
+    n = len(theta)
+    nphi = np.full(n, nphi, dtype=np.int64)
+    phi0 = np.broadcast_to(np.asarray(phi0, dtype=np.float64), (n,)).copy()
+    ofs = np.arange(n, dtype=np.int64) * nphi[0]
+    return si.Geometry(theta, nphi, phi0, np.ones(n), ofs, 1)
+
+
+def test_deriv_closed_forms():
+    """df/dtheta and df/(sin theta dphi) of single low-degree modes, written
+    out from Y_10, Y_11, Y_20, Y_21 (Condon-Shortley), including both poles
+    (where df/(sin theta dphi) takes its limit)."""
+    theta = np.array([0.0, 0.2, 1.0, 0.5 * math.pi, 2.3, math.pi])
+    nphi = 7
+    g = _rings_geometry(theta, nphi, 0.3)
+    th = np.repeat(theta, nphi)
+    ph = np.concatenate([0.3 + 2 * math.pi * np.arange(nphi) / nphi] * len(theta))
+    lmax = 3
+    n = si.nalm(lmax, lmax)
+    c10, c11 = math.sqrt(3 / (4 * math.pi)), math.sqrt(3 / (8 * math.pi))
+    c20, c21 = math.sqrt(5 / (16 * math.pi)), math.sqrt(15 / (8 * math.pi))
+    cases = [  # (l, m, re, im) -> (df/dtheta, df/(sin theta dphi))
+        (1, 0, 1.0, 0.0, -c10 * np.sin(th), 0 * th),
+        (1, 1, 1.0, 0.0, -2 * c11 * np.cos(th) * np.cos(ph), 2 * c11 * np.sin(ph)),
+        (1, 1, 0.0, 1.0, 2 * c11 * np.cos(th) * np.sin(ph), 2 * c11 * np.cos(ph)),
+        (2, 0, 1.0, 0.0, -6 * c20 * np.cos(th) * np.sin(th), 0 * th),
+        (2, 1, 1.0, 0.0, -2 * c21 * np.cos(2 * th) * np.cos(ph), 2 * c21 * np.cos(th) * np.sin(ph)),
+    ]
+    for l, m, re, im, dth, dph in cases:
+        a = np.zeros((1, 1, n, 2))
+        a[0, 0, si.alm_index(lmax, l, m)] = (re, im)
+        d = oracle.deriv_synthesis(g, lmax, lmax, a)
+        assert np.max(np.abs(d[0, 0] - dth)) < 1e-14, (l, m, re, im)
+        assert np.max(np.abs(d[0, 1] - dph)) < 1e-14, (l, m, re, im)
+
+
+def test_deriv_finite_differences():
+    """Against fourth-order central differences of the spin-0 synthesis in
+    theta and phi (random coefficients up to l = 20, rings in both
+    hemispheres and close to a pole)."""
+    lmax, h = 20, 2e-4
+    theta = np.array([0.03, 0.4, 1.2, 1.9, 2.7, 3.1])
+    nphi, phi0 = 45, 0.17
+    a = si.random_alm(lmax, lmax, 2, 0, spectrum="unit", tag=61)
+    d = oracle.deriv_synthesis(_rings_geometry(theta, nphi, phi0), lmax, lmax, a)
+
+    def f(dt, dp):
+        return oracle.synthesis(_rings_geometry(theta + dt, nphi, phi0 + dp), lmax, lmax, 0, a)[:, 0]
+
+    def d4(step):
+        return (-step(2 * h) + 8 * step(h) - 8 * step(-h) + step(-2 * h)) / (12 * h)
+
+    dth = d4(lambda x: f(x, 0.0))
+    dph = d4(lambda x: f(0.0, x)) / np.repeat(np.sin(theta), nphi)[None]
+    scale = np.max(np.abs(d))
+    assert np.max(np.abs(d[:, 0] - dth)) < 1e-8 * scale
+    assert np.max(np.abs(d[:, 1] - dph)) < 1e-8 * scale
+
+
+def test_deriv_adjoint_dot_product():
+    """<D a, g> = sum_lm fac_m Re(conj(a_lm) (D^T g)_lm) for the derivative
+    synthesis D and deriv_adjoint, on a HEALPix grid."""
+    lmax = 12
+    geom = si.healpix_geometry(4)
+    a = si.random_alm(lmax, lmax, 1, 0, spectrum="unit", tag=62)
+    gmap = si.random_map(geom, 1, 2, tag=63)
+    lhs = float(np.sum(oracle.deriv_synthesis(geom, lmax, lmax, a) * gmap))
+    dt = oracle.deriv_adjoint(geom, lmax, lmax, gmap)
+    _, ms = si.lm_arrays(lmax, lmax)
+    fac = np.where(ms == 0, 1.0, 2.0)
+    rhs = float(np.sum(fac[None, None, :] * (a[..., 0] * dt[..., 0] + a[..., 1] * dt[..., 1])))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
