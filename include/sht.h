@@ -70,7 +70,8 @@ typedef enum {
 
 enum { SHT_FP64 = 0, SHT_FP32_MFMA = 1 };
 enum { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1, SHT_ALM2MAP_ADJOINT = 2, SHT_ALM2MAP_GRAD = 3,
-       SHT_MAP2ALM_ADJOINT = 4 };
+       SHT_MAP2ALM_ADJOINT = 4, SHT_ALM2MAP_DERIV1 = 5, SHT_ALM2MAP_DERIV1_ADJOINT = 6,
+       SHT_ALM2MAP_DERIV1_GRAD = 7 };
 
 typedef struct sht_geom sht_geom;
 typedef struct sht_plan sht_plan;
@@ -159,21 +160,30 @@ void sht_plan_destroy(sht_plan *p);
    out = W Y a, the synthesis with every ring multiplied by its weight w_y
    (needs weights).  For real maps x the pair satisfies
    <x, W Y a> = sum over l, m >= 0 of fac_m Re(a_lm conj((Y^T W x)_lm)).
+   SHT_ALM2MAP_DERIV1 (Sect. 4.3, maps of first derivatives; needs a plan of
+   spin 1): in = spin-0 a_lm of a real field f, laid out [ntrans][1][nalm][2];
+   out = maps [ntrans][2][npix] holding df/dtheta and df/(sin theta dphi).
+   Computed as the spin-1 synthesis of E_lm = sqrt(l (l + 1)) a_lm, B_lm = 0.
+   SHT_ALM2MAP_DERIV1_ADJOINT: in = maps [ntrans][2][npix], out = its adjoint
+   [ntrans][1][nalm][2], sqrt(l (l + 1)) times the E part of the spin-1 Y^T;
+   SHT_ALM2MAP_DERIV1_GRAD: the same times fac_m (the gradient of a real loss).
    in and out must not overlap. */
 int sht_execute(sht_plan *p, int direction, const double *in, double *out,
                 void *hip_stream);
 
 /* Legendre step only (Eqs. 4, 5).  SHT_ALM2MAP (and SHT_MAP2ALM_ADJOINT, the
-   same Legendre step): in = a_lm, out = F phases.
+   same Legendre step): in = a_lm, out = F phases; SHT_ALM2MAP_DERIV1: in =
+   spin-0 a_lm, out = F phases of the derivative maps.
    SHT_MAP2ALM / SHT_ALM2MAP_ADJOINT / SHT_ALM2MAP_GRAD: in = G phases, out = a_lm
-   (GRAD also applies fac_m). */
+   (GRAD also applies fac_m); the DERIV1 adjoints: out = one component. */
 int sht_legendre(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 
 /* Ring FFT step only (Eqs. 3, 6).  SHT_ALM2MAP: in = F phases, out = maps.
    SHT_MAP2ALM_ADJOINT: in = F phases, out = maps times the ring weights w_y;
    SHT_MAP2ALM: in = maps, out = G phases with weights w_y;
-   SHT_ALM2MAP_ADJOINT and SHT_ALM2MAP_GRAD: the same with all weights one. */
+   SHT_ALM2MAP_ADJOINT and SHT_ALM2MAP_GRAD: the same with all weights one;
+   the DERIV1 directions as ALM2MAP (synthesis) and ALM2MAP_ADJOINT (others). */
 int sht_ring_fft(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 

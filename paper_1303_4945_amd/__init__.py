@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libsht.so")
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_EUNSUPPORTED, SHT_ESTATE = range(6)
 FP64, FP32_MFMA = 0, 1
 ALM2MAP, MAP2ALM, ALM2MAP_ADJOINT, ALM2MAP_GRAD, MAP2ALM_ADJOINT = 0, 1, 2, 3, 4
+ALM2MAP_DERIV1, ALM2MAP_DERIV1_ADJOINT, ALM2MAP_DERIV1_GRAD = 5, 6, 7
+_SYNTH_DIRECTIONS = (ALM2MAP, MAP2ALM_ADJOINT, ALM2MAP_DERIV1)
+_DERIV_DIRECTIONS = (ALM2MAP_DERIV1, ALM2MAP_DERIV1_ADJOINT, ALM2MAP_DERIV1_GRAD)
 ECP_FEJER1, ECP_FEJER2, ECP_CC = 0, 1, 2
 
 _STATUS_NAMES = {1: "SHT_EINVAL", 2: "SHT_ENOMEM", 3: "SHT_EDEVICE", 4: "SHT_EUNSUPPORTED",
@@ -229,6 +232,16 @@ class Plan:
         return (self.ntrans, self.ncomp, self.npix)
 
     @property
+    def deriv_alm_shape(self):
+        """Spin-0 coefficients of the derivative directions (spin-1 plans)."""
+        return (self.ntrans, 1, self.nalm, 2)
+
+    def out_shape(self, direction):
+        if direction in _SYNTH_DIRECTIONS:
+            return self.map_shape
+        return self.deriv_alm_shape if direction in _DERIV_DIRECTIONS else self.alm_shape
+
+    @property
     def phase_shape(self):
         return (self.ntrans, self.ncomp, self.nrings, self.mmax + 1, 2)
 
@@ -259,6 +272,19 @@ class Plan:
     def alm2map_grad(self, grad_maps, stream=None, out=None):
         """dL/d(Re a) + i dL/d(Im a) of a real loss L from dL/dmap (fac_m Y^T g)."""
         return self._run(_lib.sht_execute, ALM2MAP_GRAD, grad_maps, self.alm_shape, stream, out)
+
+    def alm2map_deriv1(self, alm, stream=None, out=None):
+        """Maps of df/dtheta and df/(sin theta dphi) from spin-0 a_lm [ntrans][1][nalm][2]
+        (Sect. 4.3; the plan must have spin 1)."""
+        return self._run(_lib.sht_execute, ALM2MAP_DERIV1, alm, self.map_shape, stream, out)
+
+    def deriv1_adjoint(self, maps, stream=None, out=None):
+        """Adjoint of alm2map_deriv1: maps [ntrans][2][npix] -> [ntrans][1][nalm][2]."""
+        return self._run(_lib.sht_execute, ALM2MAP_DERIV1_ADJOINT, maps, self.deriv_alm_shape, stream, out)
+
+    def alm2map_deriv1_grad(self, grad_maps, stream=None, out=None):
+        """Gradient of a real loss with respect to the a_lm of alm2map_deriv1."""
+        return self._run(_lib.sht_execute, ALM2MAP_DERIV1_GRAD, grad_maps, self.deriv_alm_shape, stream, out)
 
     def legendre_synth(self, alm, stream=None):
         return self._run(_lib.sht_legendre, ALM2MAP, alm, self.phase_shape, stream)
@@ -318,8 +344,7 @@ class Batch:
             if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
                 raise TypeError("expected float64 CUDA tensors")
         if outs is None:
-            shape = (lambda p: p.map_shape) if direction == ALM2MAP else (lambda p: p.alm_shape)
-            outs = [torch.empty(shape(p), dtype=torch.float64, device=x.device)
+            outs = [torch.empty(p.out_shape(direction), dtype=torch.float64, device=x.device)
                     for p, x in zip(self.plans, ins)]
         a_in = (_vp * n)(*[x.data_ptr() for x in ins])
         a_out = (_vp * n)(*[y.data_ptr() for y in outs])

@@ -82,20 +82,21 @@ int batch_enqueue(Batch &b, int direction, const double *const *in, double *cons
             ptrs.in[i] = in[i];
             ptrs.out[i] = b.plans[i]->d_phase;
         }
-        if ((rc = launch_legendre_synth_batch(b, ptrs, s))) return rc;
+        if ((rc = launch_legendre_synth_batch(b, ptrs, deriv_direction(direction), s))) return rc;
         for (int i = 0; i < np; ++i)
             if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i],
-                                        direction == SHT_MAP2ALM_ADJOINT, s)))
+                                        weighted_direction(direction), s)))
                 return rc;
     } else {
         for (int i = 0; i < np; ++i)
-            if ((rc = launch_ring_anal(*b.plans[i], in[i], b.plans[i]->d_phase, direction == SHT_MAP2ALM, s)))
+            if ((rc = launch_ring_anal(*b.plans[i], in[i], b.plans[i]->d_phase, weighted_direction(direction),
+                                       s)))
                 return rc;
         for (int i = 0; i < np; ++i) {
             ptrs.in[i] = b.plans[i]->d_phase;
             ptrs.out[i] = out[i];
         }
-        if ((rc = launch_legendre_anal_batch(b, ptrs, direction == SHT_ALM2MAP_GRAD, s))) return rc;
+        if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction), s))) return rc;
     }
     return SHT_OK;
 }
@@ -109,9 +110,9 @@ int time_synth(Plan &p, const double *alm, int reps, double &ms)
         set_error("event creation failed");
         return SHT_EDEVICE;
     }
-    int rc = launch_legendre_synth(p, alm, p.d_phase, nullptr);   // warm-up
+    int rc = launch_legendre_synth(p, alm, p.d_phase, false, nullptr);   // warm-up
     if (!rc) rc = check_hip(hipEventRecord(e0, nullptr), "autotune");
-    for (int r = 0; r < reps && !rc; ++r) rc = launch_legendre_synth(p, alm, p.d_phase, nullptr);
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_legendre_synth(p, alm, p.d_phase, false, nullptr);
     if (!rc) rc = check_hip(hipEventRecord(e1, nullptr), "autotune");
     if (!rc) rc = check_hip(hipEventSynchronize(e1), "autotune");
     float t = 0.f;

@@ -301,7 +301,7 @@ struct SynShared {
 template <int SPIN, int NCB, bool F32>
 __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
                                            const double *__restrict__ alm, double *__restrict__ phase,
-                                           int flush_chunks, SynShared<SPIN, F32> &sh)
+                                           int flush_chunks, int deriv, SynShared<SPIN, F32> &sh)
 {
     using T = typename MT<F32>::T;
     using V = typename MT<F32>::V;
@@ -337,15 +337,19 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
     bool slow = wave_any(cs.k < 0);
 
     // B operand sources: this lane's column in each column block (columns that
-    // take no part -- beyond the last transform, or Im at m = 0 -- read zeros)
+    // take no part -- beyond the last transform, Im at m = 0, B of a derivative
+    // synthesis -- read zeros).  Derivative synthesis (spin-1 plan): the input
+    // holds one component per transform, taken as E with B = 0.
+    if (!SPIN) deriv = 0;
+    const int ncin = deriv ? 1 : NCOMP;
     const double *bp[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
         const int col = i16 + 16 * cb;
         const int t = t0 + col / CPJ, o = col % CPJ;
         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
-        const bool ok = t < v.ntrans && !(m == 0 && reim);
-        bp[cb] = ok ? alm + (((int64_t)t * NCOMP + comp) * v.nalm + mbase) * 2 + reim : v.zeros;
+        const bool ok = t < v.ntrans && !(m == 0 && reim) && !(deriv && comp);
+        bp[cb] = ok ? alm + (((int64_t)t * ncin + comp) * v.nalm + mbase) * 2 + reim : v.zeros;
     }
     const bool xneg = SPIN && ((i16 & 3) == 1 || (i16 & 3) == 2);
 
@@ -386,10 +390,14 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         c0n = coef[lcl];
         f0n = flm[lcl];
     };
+    // f_l of a derivative synthesis also carries sqrt(l (l + 1)): E_lm of the
+    // gradient of a scalar field is sqrt(l (l + 1)) a_lm (a table lookup: an
+    // FP64 square root here would cost registers at the loop's peak)
     auto storeC = [&](int buf, int lc) {
         const int l = lc + lane % LC;
         const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
-        const double f = (l >= l0 && l <= lmax) ? f0n * fscale : 0.0;
+        const double kd = deriv ? v.dfac[l <= lmax ? l : lmax] : 1.0;
+        const double f = (l >= l0 && l <= lmax) ? f0n * fscale * kd : 0.0;
         if (lane < NCH * LC) cfs[buf][lane / LC][lane % LC] = chain_coef(c, lane >= LC, f);
     };
     // c f_l onto the coefficients of the chunk staged in cfs[buf] (zero outside
@@ -565,10 +573,10 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
 template <int SPIN, int NCB, bool F32>
 __global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem *__restrict__ items,
                                                        const double *__restrict__ alm,
-                                                       double *__restrict__ phase, int flush_chunks)
+                                                       double *__restrict__ phase, int flush_chunks, int deriv)
 {
     __shared__ SynShared<SPIN, F32> sh;
-    synth_item<SPIN, NCB, F32>(v, items[blockIdx.x], alm, phase, flush_chunks, sh);
+    synth_item<SPIN, NCB, F32>(v, items[blockIdx.x], alm, phase, flush_chunks, deriv, sh);
 }
 
 // Persistent form for a batch of plans: every wavefront takes items from one
@@ -577,7 +585,7 @@ template <int SPIN, int NCB, bool F32>
 __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__restrict__ views,
                                                              const BatchSynItem *__restrict__ items,
                                                              int nitems, BatchPtrs ptrs, int flush_chunks,
-                                                             unsigned *counter)
+                                                             int deriv, unsigned *counter)
 {
     __shared__ SynShared<SPIN, F32> sh;
     for (;;) {
@@ -587,7 +595,7 @@ __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__re
         if (idx >= (unsigned)nitems) break;
         const BatchSynItem bi = items[idx];
         synth_item<SPIN, NCB, F32>(views[bi.plan], bi.it, ptrs.in[bi.plan], ptrs.out[bi.plan], flush_chunks,
-                                   sh);
+                                   deriv, sh);
         __syncthreads();
     }
 }
@@ -648,7 +656,7 @@ struct AnaShared {
 template <int SPIN, int NCB, bool F32, int TPW>
 __device__ __forceinline__ void anal_item(const LegView &v, const int m, const int t0,
                                           const double *__restrict__ phase, double *__restrict__ alm,
-                                          int grad, AnaShared<SPIN, NCB, F32> &sh)
+                                          int mode, AnaShared<SPIN, NCB, F32> &sh)
 {
     using T = typename MT<F32>::T;
     using V = typename MT<F32>::V;
@@ -686,6 +694,11 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     const int rslot = SPIN ? (lane & 31) : lane;
     const int rchain = SPIN ? (lane >> 5) : 0;
     T *lam_out = lam_w + rchain * LC * LDP + rslot;
+    // mode bit 0: real-field gradient factor fac_m; bit 1 (spin-1 plans): adjoint
+    // of the derivative synthesis, whose output is sqrt(l (l + 1)) times the E
+    // component alone (one component per transform)
+    const bool grad = mode & ANA_MODE_GRAD;
+    const bool deriv = SPIN && (mode & ANA_MODE_DERIV);
 
     // this thread's output elements of a chunk: element e = tid + j NT ->
     // (row tc = transform * NCOMP + component, degree offset, re/im), consecutive
@@ -693,17 +706,20 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     // and the row advances by TCS per j.
     static_assert((NT / 2) % LC == 0, "output element mapping");
     constexpr int TCS = NT / 2 / LC;
+    static_assert(TCS % 2 == 0, "rows of one thread share their component");
     const int oreim = tid & 1, oloff = (tid >> 1) % LC, tc0 = (tid >> 1) / LC;
     unsigned ovalid = 0;   // bit j: element j exists (row in this group, transform < ntrans)
 #pragma unroll
     for (int j = 0; j < OPT; ++j) {
         const int tc = tc0 + TCS * j;
-        if (tc < NCOL / 2 && t0 + tc / NCOMP < v.ntrans) ovalid |= 1u << j;
+        if (tc < NCOL / 2 && t0 + tc / NCOMP < v.ntrans && !(deriv && (tc % NCOMP))) ovalid |= 1u << j;
     }
-    const int64_t ostride = (int64_t)TCS * v.nalm * 2;
+    // output row of (transform, component): t NCOMP + comp, or t alone (derivative adjoint)
+    const int64_t ostride = (int64_t)(deriv ? TCS / NCOMP : TCS) * v.nalm * 2;
+    const int64_t orow0 = deriv ? (int64_t)t0 + tc0 / NCOMP : (int64_t)t0 * NCOMP + tc0;
     // row tc0 of this group (only dereferenced for valid elements; loads of
     // invalid ones go to the start of alm instead)
-    double *const obase = alm + (((int64_t)t0 * NCOMP + tc0) * v.nalm + mbase) * 2 + oreim;
+    double *const obase = alm + (orow0 * v.nalm + mbase) * 2 + oreim;
 
     // degrees m .. l0-1 (spin s > m) are zero by convention
     {
@@ -713,8 +729,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
             const int rest = e / nz;
             const int reim = rest & 1, tc = rest >> 1;
             const int t = t0 + tc / NCOMP, comp = tc % NCOMP;
-            if (t < v.ntrans)
-                alm[(((int64_t)t * NCOMP + comp) * v.nalm + mbase + l) * 2 + reim] = 0.0;
+            if (t < v.ntrans && !(deriv && comp))
+                alm[(((int64_t)t * (deriv ? 1 : NCOMP) + comp) * v.nalm + mbase + l) * 2 + reim] = 0.0;
         }
     }
 
@@ -808,7 +824,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 for (int cb = 0; cb < NCB; ++cb) acc[p][cb] = V{0, 0, 0, 0};
             {
                 const int l = lc + (lane % LC);
-                const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) : 0.0;
+                const double kd = deriv ? v.dfac[l <= lmax ? l : lmax] : 1.0;
+                const double f = (l >= l0 && l <= lmax) ? f0n * (SPIN ? 0.5 : 1.0) * kd : 0.0;
                 if (wave == 0 && lane < LC) sh.fls[PSEP ? (cidx & 1) : 0][lane] = f;
                 if (any_active) {
                     const double4 c = (l >= l0 && l < lmax) ? c0n : double4{0, 0, 0, 0};
@@ -908,17 +925,17 @@ template <int SPIN, int NCB, bool F32>
 __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
                                                                   const double *__restrict__ phase,
                                                                   double *__restrict__ alm,
-                                                                  int jobs_per_group, int grad)
+                                                                  int jobs_per_group, int mode)
 {
     __shared__ AnaShared<SPIN, NCB, F32> sh;
-    anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(v, mlist[blockIdx.x], (int)blockIdx.y * jobs_per_group, phase, alm, grad, sh);
+    anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(v, mlist[blockIdx.x], (int)blockIdx.y * jobs_per_group, phase, alm, mode, sh);
 }
 
 // Persistent form for a batch of plans (one queue, atomic counter).
 template <int SPIN, int NCB, bool F32>
 __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal_batch(const LegView *__restrict__ views,
                                                                         const BatchAnaItem *__restrict__ items,
-                                                                        int nitems, BatchPtrs ptrs, int grad,
+                                                                        int nitems, BatchPtrs ptrs, int mode,
                                                                         unsigned *counter)
 {
     __shared__ AnaShared<SPIN, NCB, F32> sh;
@@ -930,7 +947,7 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal_batch(const Le
         __syncthreads();
         if (idx >= (unsigned)nitems) break;
         const BatchAnaItem bi = items[idx];
-        anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(views[bi.plan], bi.m, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], grad, sh);
+        anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(views[bi.plan], bi.m, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], mode, sh);
         __syncthreads();
     }
 }
@@ -962,34 +979,34 @@ int synth_ncb_default(int spin, int ntrans, int precision)
 
 template <int SPIN, int NCB, bool F32>
 static void launch_synth_t(const Plan &p, const LegView &v, const double *alm, double *phase,
-                           hipStream_t s)
+                           int deriv, hipStream_t s)
 {
     hipLaunchKernelGGL((k_legendre_synth<SPIN, NCB, F32>), dim3((unsigned)p.synth_items.size()), dim3(64),
-                       0, s, v, p.d_synth_items, alm, phase, p.flush_chunks);
+                       0, s, v, p.d_synth_items, alm, phase, p.flush_chunks, deriv);
 }
 
 template <int SPIN, int NCB, bool F32>
 static void launch_anal_t(const Plan &p, const LegView &v, const double *phase, double *alm,
-                          int grad, hipStream_t s)
+                          int mode, hipStream_t s)
 {
     const int jpg = NCB * 16 / (SPIN ? 4 : 2);
     dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + jpg - 1) / jpg));
     hipLaunchKernelGGL((k_legendre_anal<SPIN, NCB, F32>), grid, dim3(64 * LEG_NW), 0, s, v,
-                       p.d_anal_ms, phase, alm, jpg, grad);
+                       p.d_anal_ms, phase, alm, jpg, mode);
 }
 
 template <bool F32>
 static int dispatch_synth(const Plan &p, const LegView &v, const double *alm, double *phase,
-                          hipStream_t s)
+                          int deriv, hipStream_t s)
 {
     const int ncb = p.synth_ncb;
     if (p.spin == 0) {
-        if (ncb == 1) launch_synth_t<0, 1, F32>(p, v, alm, phase, s);
-        else if (ncb == 2) launch_synth_t<0, 2, F32>(p, v, alm, phase, s);
+        if (ncb == 1) launch_synth_t<0, 1, F32>(p, v, alm, phase, 0, s);
+        else if (ncb == 2) launch_synth_t<0, 2, F32>(p, v, alm, phase, 0, s);
         else return SHT_EINVAL;
     } else {
-        if (ncb == 1) launch_synth_t<2, 1, F32>(p, v, alm, phase, s);
-        else if (ncb == 2) launch_synth_t<2, 2, F32>(p, v, alm, phase, s);
+        if (ncb == 1) launch_synth_t<2, 1, F32>(p, v, alm, phase, deriv, s);
+        else if (ncb == 2) launch_synth_t<2, 2, F32>(p, v, alm, phase, deriv, s);
         else return SHT_EINVAL;
     }
     return SHT_OK;
@@ -997,24 +1014,25 @@ static int dispatch_synth(const Plan &p, const LegView &v, const double *alm, do
 
 template <bool F32>
 static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, double *alm,
-                          int grad, hipStream_t s)
+                          int mode, hipStream_t s)
 {
     const int ncb = anal_ncb(p.spin, p.ntrans);
     if (p.spin == 0) {
-        if (ncb == 1) launch_anal_t<0, 1, F32>(p, v, phase, alm, grad, s);
-        else launch_anal_t<0, 2, F32>(p, v, phase, alm, grad, s);
+        if (ncb == 1) launch_anal_t<0, 1, F32>(p, v, phase, alm, mode, s);
+        else launch_anal_t<0, 2, F32>(p, v, phase, alm, mode, s);
     } else {
-        if (ncb == 1) launch_anal_t<2, 1, F32>(p, v, phase, alm, grad, s);
-        else launch_anal_t<2, 2, F32>(p, v, phase, alm, grad, s);
+        if (ncb == 1) launch_anal_t<2, 1, F32>(p, v, phase, alm, mode, s);
+        else launch_anal_t<2, 2, F32>(p, v, phase, alm, mode, s);
     }
 }
 
-int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipStream_t s)
+int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool deriv, hipStream_t s)
 {
     if (p.synth_items.empty()) return SHT_OK;
     const LegView v = make_leg_view(p);
-    const int rc = p.precision == SHT_FP32_MFMA ? dispatch_synth<true>(p, v, alm, phase, s)
-                                                : dispatch_synth<false>(p, v, alm, phase, s);
+    const int d = deriv ? 1 : 0;
+    const int rc = p.precision == SHT_FP32_MFMA ? dispatch_synth<true>(p, v, alm, phase, d, s)
+                                                : dispatch_synth<false>(p, v, alm, phase, d, s);
     if (rc) {
         set_error("synthesis column blocks %d not available", p.synth_ncb);
         return rc;
@@ -1022,11 +1040,11 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipSt
     return check_hip(hipGetLastError(), "legendre synthesis launch");
 }
 
-int launch_legendre_anal(const Plan &p, const double *phase, double *alm, bool grad, hipStream_t s)
+int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s)
 {
     const LegView v = make_leg_view(p);
-    if (p.precision == SHT_FP32_MFMA) dispatch_anal<true>(p, v, phase, alm, grad ? 1 : 0, s);
-    else dispatch_anal<false>(p, v, phase, alm, grad ? 1 : 0, s);
+    if (p.precision == SHT_FP32_MFMA) dispatch_anal<true>(p, v, phase, alm, mode, s);
+    else dispatch_anal<false>(p, v, phase, alm, mode, s);
     return check_hip(hipGetLastError(), "legendre analysis launch");
 }
 
@@ -1048,57 +1066,58 @@ static int persistent_groups(K kernel, int threads)
 }
 
 template <int SPIN, int NCB, bool F32>
-static void launch_synth_batch_t(const Batch &b, const BatchPtrs &ptrs, hipStream_t s)
+static void launch_synth_batch_t(const Batch &b, const BatchPtrs &ptrs, int deriv, hipStream_t s)
 {
     auto k = k_legendre_synth_batch<SPIN, NCB, F32>;
     static const int groups = persistent_groups(k, 64);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
     hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64), 0, s, b.d_views, b.d_syn, b.nsyn, ptrs,
-                       b.plans[0]->flush_chunks, b.d_counter);
+                       b.plans[0]->flush_chunks, deriv, b.d_counter);
 }
 
 template <int SPIN, int NCB, bool F32>
-static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, bool grad, hipStream_t s)
+static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     auto k = k_legendre_anal_batch<SPIN, NCB, F32>;
     static const int groups = persistent_groups(k, 64 * LEG_NW);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
     hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * LEG_NW), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
-                       grad ? 1 : 0, b.d_counter);
+                       mode, b.d_counter);
 }
 
-int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, hipStream_t s)
+int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s)
 {
     if (b.nsyn == 0) return SHT_OK;
     const bool f32 = b.precision == SHT_FP32_MFMA;
+    const int d = deriv ? 1 : 0;
     const int key = (b.spin ? 4 : 0) + (b.syn_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
     switch (key) {
-    case 0: launch_synth_batch_t<0, 1, false>(b, ptrs, s); break;
-    case 1: launch_synth_batch_t<0, 1, true>(b, ptrs, s); break;
-    case 2: launch_synth_batch_t<0, 2, false>(b, ptrs, s); break;
-    case 3: launch_synth_batch_t<0, 2, true>(b, ptrs, s); break;
-    case 4: launch_synth_batch_t<2, 1, false>(b, ptrs, s); break;
-    case 5: launch_synth_batch_t<2, 1, true>(b, ptrs, s); break;
-    case 6: launch_synth_batch_t<2, 2, false>(b, ptrs, s); break;
-    default: launch_synth_batch_t<2, 2, true>(b, ptrs, s); break;
+    case 0: launch_synth_batch_t<0, 1, false>(b, ptrs, 0, s); break;
+    case 1: launch_synth_batch_t<0, 1, true>(b, ptrs, 0, s); break;
+    case 2: launch_synth_batch_t<0, 2, false>(b, ptrs, 0, s); break;
+    case 3: launch_synth_batch_t<0, 2, true>(b, ptrs, 0, s); break;
+    case 4: launch_synth_batch_t<2, 1, false>(b, ptrs, d, s); break;
+    case 5: launch_synth_batch_t<2, 1, true>(b, ptrs, d, s); break;
+    case 6: launch_synth_batch_t<2, 2, false>(b, ptrs, d, s); break;
+    default: launch_synth_batch_t<2, 2, true>(b, ptrs, d, s); break;
     }
     return check_hip(hipGetLastError(), "batch legendre synthesis launch");
 }
 
-int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, bool grad, hipStream_t s)
+int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     if (b.nana == 0) return SHT_OK;
     const bool f32 = b.precision == SHT_FP32_MFMA;
     const int key = (b.spin ? 4 : 0) + (b.ana_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
     switch (key) {
-    case 0: launch_anal_batch_t<0, 1, false>(b, ptrs, grad, s); break;
-    case 1: launch_anal_batch_t<0, 1, true>(b, ptrs, grad, s); break;
-    case 2: launch_anal_batch_t<0, 2, false>(b, ptrs, grad, s); break;
-    case 3: launch_anal_batch_t<0, 2, true>(b, ptrs, grad, s); break;
-    case 4: launch_anal_batch_t<2, 1, false>(b, ptrs, grad, s); break;
-    case 5: launch_anal_batch_t<2, 1, true>(b, ptrs, grad, s); break;
-    case 6: launch_anal_batch_t<2, 2, false>(b, ptrs, grad, s); break;
-    default: launch_anal_batch_t<2, 2, true>(b, ptrs, grad, s); break;
+    case 0: launch_anal_batch_t<0, 1, false>(b, ptrs, mode, s); break;
+    case 1: launch_anal_batch_t<0, 1, true>(b, ptrs, mode, s); break;
+    case 2: launch_anal_batch_t<0, 2, false>(b, ptrs, mode, s); break;
+    case 3: launch_anal_batch_t<0, 2, true>(b, ptrs, mode, s); break;
+    case 4: launch_anal_batch_t<2, 1, false>(b, ptrs, mode, s); break;
+    case 5: launch_anal_batch_t<2, 1, true>(b, ptrs, mode, s); break;
+    case 6: launch_anal_batch_t<2, 2, false>(b, ptrs, mode, s); break;
+    default: launch_anal_batch_t<2, 2, true>(b, ptrs, mode, s); break;
     }
     return check_hip(hipGetLastError(), "batch legendre analysis launch");
 }

@@ -405,6 +405,7 @@ static void plan_free_device(Plan *p)
     dev_free(p->d_coef); dev_free(p->d_fl); dev_free(p->d_coef_ofs); dev_free(p->d_start);
     dev_free(p->d_tile_mlim); dev_free(p->d_synth_items); dev_free(p->d_anal_ms);
     dev_free(p->d_zeros);
+    dev_free(p->d_dfac);
     dev_free(p->d_phase);
     fft_plan_free(p->fft);
     p->d_slot_cos = p->d_slot_sin = p->d_slot_chalf = p->d_slot_shalf = nullptr;
@@ -412,6 +413,7 @@ static void plan_free_device(Plan *p)
     p->d_coef = nullptr; p->d_fl = nullptr; p->d_coef_ofs = nullptr; p->d_start = nullptr;
     p->d_tile_mlim = nullptr; p->d_synth_items = nullptr; p->d_anal_ms = nullptr;
     p->d_zeros = nullptr;
+    p->d_dfac = nullptr;
     p->d_phase = nullptr;
 }
 
@@ -732,6 +734,10 @@ static int plan_build(Plan &p)
         const size_t zb = (size_t)2 * (p.lmax + 2) * sizeof(double);
         if ((rc = dev_alloc((void **)&p.d_zeros, zb, "zero operands"))) return rc;
         if ((rc = check_hip(hipMemset(p.d_zeros, 0, zb), "zero operands"))) return rc;
+        std::vector<double> df(p.lmax + 2);
+        for (int l = 0; l <= p.lmax + 1; ++l) df[l] = (double)sqrtl((long double)l * (long double)(l + 1));
+        if ((rc = dev_alloc((void **)&p.d_dfac, df.size() * sizeof(double), "derivative factors"))) return rc;
+        if ((rc = dev_upload(p.d_dfac, df.data(), df.size() * sizeof(double), "upload"))) return rc;
     }
     p.synth_ncb = synth_ncb_default(p.spin, p.ntrans, p.precision);
     if ((rc = build_synth_items(p))) return rc;
@@ -762,6 +768,7 @@ LegView make_leg_view(const Plan &p)
     v.coef = p.d_coef; v.fl = p.d_fl; v.coef_ofs = p.d_coef_ofs; v.start = p.d_start;
     v.tile_mlim = p.d_tile_mlim;
     v.zeros = p.d_zeros;
+    v.dfac = p.d_dfac;
     v.nalm = p.nalm;
     return v;
 }
@@ -787,11 +794,16 @@ int check_exec_args(const Plan *p, int direction, const void *in, const void *ou
         return SHT_EINVAL;
     }
     if (!in || !out) { set_error("in and out must be device pointers"); return SHT_EINVAL; }
-    if ((direction == SHT_MAP2ALM || direction == SHT_MAP2ALM_ADJOINT) && !p->geom.has_weight && !stage_leg) {
+    if (weighted_direction(direction) && !p->geom.has_weight && !stage_leg) {
         set_error("geometry has no ring weights: analysis and its adjoint unavailable");
         return SHT_EINVAL;
     }
-    const size_t alm_b = (size_t)p->ntrans * p->ncomp * p->nalm * 16;
+    if (deriv_direction(direction) && p->spin != 1) {
+        set_error("first-derivative directions need a plan of spin 1 (plan spin %d)", p->spin);
+        return SHT_EINVAL;
+    }
+    const int alm_comp = deriv_direction(direction) ? 1 : p->ncomp;
+    const size_t alm_b = (size_t)p->ntrans * alm_comp * p->nalm * 16;
     const size_t map_b = (size_t)p->ntrans * p->ncomp * p->geom.npix * 8;
     const size_t ph_b = (size_t)p->phase_elems * 16;
     size_t in_b, out_b;
@@ -894,11 +906,11 @@ int sht_execute(sht_plan *h, int direction, const double *in, double *out, void 
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     if (synth_direction(direction)) {
-        if ((rc = launch_legendre_synth(*p, in, p->d_phase, s))) return rc;
-        if ((rc = launch_ring_synth(*p, p->d_phase, out, direction == SHT_MAP2ALM_ADJOINT, s))) return rc;
+        if ((rc = launch_legendre_synth(*p, in, p->d_phase, deriv_direction(direction), s))) return rc;
+        if ((rc = launch_ring_synth(*p, p->d_phase, out, weighted_direction(direction), s))) return rc;
     } else {
-        if ((rc = launch_ring_anal(*p, in, p->d_phase, direction == SHT_MAP2ALM, s))) return rc;
-        if ((rc = launch_legendre_anal(*p, p->d_phase, out, direction == SHT_ALM2MAP_GRAD, s))) return rc;
+        if ((rc = launch_ring_anal(*p, in, p->d_phase, weighted_direction(direction), s))) return rc;
+        if ((rc = launch_legendre_anal(*p, p->d_phase, out, anal_mode(direction), s))) return rc;
     }
     return finish_launch("sht_execute");
 }
@@ -910,8 +922,8 @@ int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, false, true);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (synth_direction(direction)) rc = launch_legendre_synth(*p, in, out, s);
-    else rc = launch_legendre_anal(*p, in, out, direction == SHT_ALM2MAP_GRAD, s);
+    if (synth_direction(direction)) rc = launch_legendre_synth(*p, in, out, deriv_direction(direction), s);
+    else rc = launch_legendre_anal(*p, in, out, anal_mode(direction), s);
     if (rc) return rc;
     return finish_launch("sht_legendre");
 }
@@ -923,8 +935,8 @@ int sht_ring_fft(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, true, false);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (synth_direction(direction)) rc = launch_ring_synth(*p, in, out, direction == SHT_MAP2ALM_ADJOINT, s);
-    else rc = launch_ring_anal(*p, in, out, direction == SHT_MAP2ALM, s);
+    if (synth_direction(direction)) rc = launch_ring_synth(*p, in, out, weighted_direction(direction), s);
+    else rc = launch_ring_anal(*p, in, out, weighted_direction(direction), s);
     if (rc) return rc;
     return finish_launch("sht_ring_fft");
 }

@@ -84,6 +84,7 @@ struct LegView {
     const StartCoef *start;     // [m][chain] chain 0: +s (or 0), chain 1: -s
     const int *tile_mlim;       // per tile: largest m with an active slot (-1: none)
     const double *zeros;        // 2 (lmax + 1) zeros: operand source of unused columns
+    const double *dfac;         // sqrt(l (l + 1)), l = 0 .. lmax + 1 (derivative synthesis)
     int64_t nalm;
 };
 
@@ -129,6 +130,7 @@ struct Plan {
     StartCoef *d_start = nullptr;
     int *d_tile_mlim = nullptr;
     double *d_zeros = nullptr;
+    double *d_dfac = nullptr;
     WaveItem *d_synth_items = nullptr;
     int *d_anal_ms = nullptr;
     double *d_phase = nullptr;       // F / G workspace
@@ -144,10 +146,28 @@ constexpr int MAX_BATCH_PLANS = 64;
 
 // Legendre-step operands of the plans of a batch, passed by value to the
 // persistent kernels (so that a captured graph holds them as parameters).
-// directions of sht_execute (SHT_ALM2MAP .. SHT_MAP2ALM_ADJOINT); the two
-// that go from a_lm to maps run the synthesis kernels
-constexpr int NUM_DIRECTIONS = 5;
-inline bool synth_direction(int d) { return d == 0 || d == 4; }
+// directions of sht_execute (SHT_ALM2MAP .. SHT_ALM2MAP_DERIV1_GRAD); the
+// ones that go from a_lm to maps run the synthesis kernels
+constexpr int NUM_DIRECTIONS = 8;
+inline bool synth_direction(int d)
+{
+    return d == SHT_ALM2MAP || d == SHT_MAP2ALM_ADJOINT || d == SHT_ALM2MAP_DERIV1;
+}
+// first-derivative synthesis and its adjoints: spin-1 plans, one a_lm component
+inline bool deriv_direction(int d)
+{
+    return d == SHT_ALM2MAP_DERIV1 || d == SHT_ALM2MAP_DERIV1_ADJOINT || d == SHT_ALM2MAP_DERIV1_GRAD;
+}
+// ring weights in the FFT step: analysis and the adjoint of analysis
+inline bool weighted_direction(int d) { return d == SHT_MAP2ALM || d == SHT_MAP2ALM_ADJOINT; }
+// analysis kernel mode bits
+constexpr int ANA_MODE_GRAD = 1;    // real-field gradient factor fac_m
+constexpr int ANA_MODE_DERIV = 2;   // adjoint of the derivative synthesis
+inline int anal_mode(int d)
+{
+    return ((d == SHT_ALM2MAP_GRAD || d == SHT_ALM2MAP_DERIV1_GRAD) ? ANA_MODE_GRAD : 0) |
+           (deriv_direction(d) ? ANA_MODE_DERIV : 0);
+}
 
 struct BatchPtrs {
     const double *in[MAX_BATCH_PLANS];
@@ -172,14 +192,14 @@ struct Batch {
 LegView make_leg_view(const Plan &p);
 
 // Legendre step launchers (legendre.hip)
-int launch_legendre_synth(const Plan &p, const double *alm, double *phase, hipStream_t s);
+int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool deriv, hipStream_t s);
 int synth_ncb_default(int spin, int ntrans, int precision);
 int build_synth_items(Plan &p);
-int launch_legendre_anal(const Plan &p, const double *phase, double *alm, bool grad, hipStream_t s);
+int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s);
 
 // persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
-int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, hipStream_t s);
-int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, bool grad, hipStream_t s);
+int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s);
+int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s);
 int anal_ncb(int spin, int ntrans);
 
 // ring FFT (ringfft.hip)
