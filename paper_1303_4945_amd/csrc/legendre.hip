@@ -636,6 +636,11 @@ struct AnaShape {
     static constexpr int LDP = SPT + 1;
     static constexpr int LAMW = NCH * ANA_LC * LDP;
 };
+// LDS slot of partial-sum element e: rows of 64 elements padded by two.  The
+// sixteen lanes of one accumulator store cover eight rows of 64 (transform and
+// component) at the same offset and re/im, which unpadded fall on two banks.
+__device__ __forceinline__ constexpr int psidx(int e) { return e + 2 * (e >> 6); }
+
 template <int SPIN, int NCB, bool F32>
 struct AnaShared {
     // FP32 form: the partial sums (FP32 products) get a region of their own,
@@ -645,10 +650,11 @@ struct AnaShared {
     static constexpr bool PSEP = F32;
     static constexpr int LAMB = AnaShape<SPIN, F32>::LAMW * (int)sizeof(typename MT<F32>::T);
     static constexpr int NOUT = ANA_LC * NCB * 16;
-    static constexpr int NOUTB = NOUT * 8;
+    static constexpr int NOUTP = NOUT + 2 * (NOUT / 64);   // padded (psidx)
+    static constexpr int NOUTB = NOUTP * 8;
     static constexpr int REG_D = ((PSEP ? LAMB : (LAMB > NOUTB ? LAMB : NOUTB)) + 7) / 8;
     double smem[LEG_NW * REG_D];
-    float psum[PSEP ? 2 * LEG_NW * NOUT : 1];
+    float psum[PSEP ? 2 * LEG_NW * NOUTP : 1];
     double4 cfs[LEG_NW][SPIN ? 2 : 1][ANA_LC];
     double fls[PSEP ? 2 : 1][ANA_LC];   // c f_l of the chunk's degrees (c = 1/2 for spin 2), applied to the sums
 };
@@ -670,6 +676,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     constexpr int CPJ = SPIN ? 4 : 2;  // columns per transform
     constexpr int NCOL = NCB * 16;
     constexpr int NOUT = LC * NCOL;    // output elements per chunk
+    constexpr int NOUTP = AnaShared<SPIN, NCB, F32>::NOUTP;
+    static_assert(NOUT % 64 == 0 && NOUTP == NOUT + 2 * (NOUT / 64), "partial-sum layout");
     constexpr int OPT = (NOUT + NT - 1) / NT;
     constexpr int LAMW = NCH * LC * LDP;   // lambda elements per wavefront
     // per wavefront: lambda [chain][row][LDP] (rows: even degree offsets, then
@@ -893,9 +901,9 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                         const int e = (((tl * NCOMP + comp) * LC) + p + 2 * row) * 2 + reim;
                         if constexpr (PSEP)
-                            sh.psum[((cidx & 1) * LEG_NW + wave) * NOUT + e] = any_active ? (float)acc[p][cb][r] : 0.0f;
+                            sh.psum[((cidx & 1) * LEG_NW + wave) * NOUTP + psidx(e)] = any_active ? (float)acc[p][cb][r] : 0.0f;
                         else
-                            part_w[e] = any_active ? (double)acc[p][cb][r] : 0.0;
+                            part_w[psidx(e)] = any_active ? (double)acc[p][cb][r] : 0.0;
                     }
             __syncthreads();
 #pragma unroll
@@ -906,8 +914,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 double s = 0.0;
 #pragma unroll
                 for (int w = 0; w < LEG_NW; ++w) {
-                    if constexpr (PSEP) s += (double)sh.psum[((cidx & 1) * LEG_NW + w) * NOUT + e];
-                    else s += smem[w * REG_D + e];
+                    if constexpr (PSEP) s += (double)sh.psum[((cidx & 1) * LEG_NW + w) * NOUTP + psidx(e)];
+                    else s += smem[w * REG_D + psidx(e)];
                 }
                 s *= sh.fls[PSEP ? (cidx & 1) : 0][oloff];
                 if (grad && m > 0) s *= 2.0;   // fac_m of the real-field gradient
