@@ -29,8 +29,8 @@
 //   U_re = -B_re W - E_im X,  U_im = -B_im W + E_re X.
 //
 // Analysis (Eq. 5), per m: out[l][col] = sum_slot Lambda[l][slot] G[slot][col]
-// with the ring pair folded into G_t +- G_(pi-t); a work group of LEG_NW
-// wavefronts walks the active tiles LEG_NW * ana_tpw at a time, reduces the
+// with the ring pair folded into G_t +- G_(pi-t); a work group of ana_nw
+// wavefronts walks the active tiles ana_nw * ana_tpw at a time, reduces the
 // wavefronts' partial sums in LDS and accumulates them into the output in a
 // fixed order (deterministic, no atomics).
 #include <hip/hip_runtime.h>
@@ -619,7 +619,7 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Work group = one m and a group of transforms.  The m's active slot tiles are
-// taken LEG_NW * TPW at a time (TPW per wavefront).  For every chunk of
+// taken NW * TPW at a time (TPW per wavefront).  For every chunk of
 // degrees each wavefront runs the recursion of one of its tiles (lane =
 // chain * 32 + slot, or slot) into its own LDS region, multiplies lambda^T (16
 // degrees of one parity x 4 slots) with that tile's phases held in registers
@@ -645,17 +645,19 @@ template <int SPIN, int NCB, bool F32>
 struct AnaShared {
     // FP32 form: the partial sums (FP32 products) get a region of their own,
     // double-buffered by chunk, so one work-group barrier per chunk suffices;
-    // the FP64 partial sums reuse the lambda region (two barriers per chunk)
-    // because a second region would not leave room for two work groups per CU
+    // the FP64 partial sums reuse the lambda region (two barriers per chunk):
+    // a second region would not fit the 160 KB of LDS next to eight wavefronts'
+    // lambda
     static constexpr bool PSEP = F32;
     static constexpr int LAMB = AnaShape<SPIN, F32>::LAMW * (int)sizeof(typename MT<F32>::T);
     static constexpr int NOUT = ANA_LC * NCB * 16;
     static constexpr int NOUTP = NOUT + 2 * (NOUT / 64);   // padded (psidx)
     static constexpr int NOUTB = NOUTP * 8;
     static constexpr int REG_D = ((PSEP ? LAMB : (LAMB > NOUTB ? LAMB : NOUTB)) + 7) / 8;
-    double smem[LEG_NW * REG_D];
-    float psum[PSEP ? 2 * LEG_NW * NOUTP : 1];
-    double4 cfs[LEG_NW][SPIN ? 2 : 1][ANA_LC];
+    static constexpr int NW = ana_nw(F32);
+    double smem[NW * REG_D];
+    float psum[PSEP ? 2 * NW * NOUTP : 1];
+    double4 cfs[NW][SPIN ? 2 : 1][ANA_LC];
     double fls[PSEP ? 2 : 1][ANA_LC];   // c f_l of the chunk's degrees (c = 1/2 for spin 2), applied to the sums
 };
 
@@ -672,7 +674,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     constexpr int NCH = SPIN ? 2 : 1;
     constexpr int NCOMP = SPIN ? 2 : 1;
     constexpr int LDP = SPT + 1;       // padded LDS row
-    constexpr int NT = 64 * LEG_NW;
+    constexpr int NW = ana_nw(F32);
+    constexpr int NT = 64 * NW;
     constexpr int CPJ = SPIN ? 4 : 2;  // columns per transform
     constexpr int NCOL = NCB * 16;
     constexpr int NOUT = LC * NCOL;    // output elements per chunk
@@ -755,11 +758,11 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
         for (int i = 0; i < TPW; ++i) ptile[i] = -1;
         {
             int k = 0;
-            for (; tscan < v.ntiles && k < LEG_NW * TPW; ++tscan) {
+            for (; tscan < v.ntiles && k < NW * TPW; ++tscan) {
                 if (v.tile_mlim[tscan] < m) continue;
 #pragma unroll
                 for (int i = 0; i < TPW; ++i)
-                    if (k == i * LEG_NW + wave) ptile[i] = tscan;
+                    if (k == i * NW + wave) ptile[i] = tscan;
                 ++k;
             }
             tcount += k;
@@ -901,7 +904,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                         const int e = (((tl * NCOMP + comp) * LC) + p + 2 * row) * 2 + reim;
                         if constexpr (PSEP)
-                            sh.psum[((cidx & 1) * LEG_NW + wave) * NOUTP + psidx(e)] = any_active ? (float)acc[p][cb][r] : 0.0f;
+                            sh.psum[((cidx & 1) * NW + wave) * NOUTP + psidx(e)] = any_active ? (float)acc[p][cb][r] : 0.0f;
                         else
                             part_w[psidx(e)] = any_active ? (double)acc[p][cb][r] : 0.0;
                     }
@@ -913,8 +916,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                 if (!((ovalid >> j) & 1) || l < l0 || l > lmax) continue;
                 double s = 0.0;
 #pragma unroll
-                for (int w = 0; w < LEG_NW; ++w) {
-                    if constexpr (PSEP) s += (double)sh.psum[((cidx & 1) * LEG_NW + w) * NOUTP + psidx(e)];
+                for (int w = 0; w < NW; ++w) {
+                    if constexpr (PSEP) s += (double)sh.psum[((cidx & 1) * NW + w) * NOUTP + psidx(e)];
                     else s += smem[w * REG_D + psidx(e)];
                 }
                 s *= sh.fls[PSEP ? (cidx & 1) : 0][oloff];
@@ -930,7 +933,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
 }
 
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
+__global__ __launch_bounds__(64 * ana_nw(F32), 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
                                                                   const double *__restrict__ phase,
                                                                   double *__restrict__ alm,
                                                                   int jobs_per_group, int mode)
@@ -941,7 +944,7 @@ __global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal(LegView v, con
 
 // Persistent form for a batch of plans (one queue, atomic counter).
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64 * LEG_NW, 2) void k_legendre_anal_batch(const LegView *__restrict__ views,
+__global__ __launch_bounds__(64 * ana_nw(F32), 2) void k_legendre_anal_batch(const LegView *__restrict__ views,
                                                                         const BatchAnaItem *__restrict__ items,
                                                                         int nitems, BatchPtrs ptrs, int mode,
                                                                         unsigned *counter)
@@ -999,7 +1002,7 @@ static void launch_anal_t(const Plan &p, const LegView &v, const double *phase, 
 {
     const int jpg = NCB * 16 / (SPIN ? 4 : 2);
     dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + jpg - 1) / jpg));
-    hipLaunchKernelGGL((k_legendre_anal<SPIN, NCB, F32>), grid, dim3(64 * LEG_NW), 0, s, v,
+    hipLaunchKernelGGL((k_legendre_anal<SPIN, NCB, F32>), grid, dim3(64 * ana_nw(F32)), 0, s, v,
                        p.d_anal_ms, phase, alm, jpg, mode);
 }
 
@@ -1087,9 +1090,9 @@ template <int SPIN, int NCB, bool F32>
 static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     auto k = k_legendre_anal_batch<SPIN, NCB, F32>;
-    static const int groups = persistent_groups(k, 64 * LEG_NW);
+    static const int groups = persistent_groups(k, 64 * ana_nw(F32));
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
-    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * LEG_NW), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
+    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * ana_nw(F32)), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
                        mode, b.d_counter);
 }
 

@@ -37,7 +37,10 @@ struct SlotHost {
     double chalf = 0, shalf = 0;  // cos t/2, sin t/2
 };
 
-constexpr int LEG_NW = 4;       // wavefronts per analysis work group
+// wavefronts per analysis work group: eight in FP64 (half the passes over a_lm
+// of four; the LDS then holds one work group per CU), four in the FP32 form
+// (whose separate partial-sum buffers would not fit eight)
+constexpr int ana_nw(bool f32) { return f32 ? 4 : 8; }
 constexpr int NUM_XCD = 8;      // accelerator dies of the MI355X (work groups go round robin)
 
 // Synthesis work item of one wavefront: one m, one slot tile, one group of
