@@ -61,7 +61,7 @@ void anal_queue(const Batch &b, std::vector<BatchAnaItem> &q)
         for (int m = 0; m <= p.mmax; ++m) {
             int act = 0;
             for (int t = 0; t < p.ntiles; ++t) act += p.tile_mlim[t] >= m;
-            const int nw = ana_nw(b.precision == SHT_FP32_MFMA);
+            const int nw = ana_nw(b.precision == SHT_FP32_MFMA, b.spin != 0);
             const double cost = (double)(p.lmax + 1 - std::max(m, p.spin)) * (double)((act + nw - 1) / nw + 1);
             for (int t0 = 0; t0 < p.ntrans; t0 += jpg) v.push_back({cost, BatchAnaItem{pi, m, t0, 0}});
         }

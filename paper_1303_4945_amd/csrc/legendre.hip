@@ -654,7 +654,7 @@ struct AnaShared {
     static constexpr int NOUTP = NOUT + 2 * (NOUT / 64);   // padded (psidx)
     static constexpr int NOUTB = NOUTP * 8;
     static constexpr int REG_D = ((PSEP ? LAMB : (LAMB > NOUTB ? LAMB : NOUTB)) + 7) / 8;
-    static constexpr int NW = ana_nw(F32);
+    static constexpr int NW = ana_nw(F32, SPIN != 0);
     double smem[NW * REG_D];
     float psum[PSEP ? 2 * NW * NOUTP : 1];
     double4 cfs[NW][SPIN ? 2 : 1][ANA_LC];
@@ -674,7 +674,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     constexpr int NCH = SPIN ? 2 : 1;
     constexpr int NCOMP = SPIN ? 2 : 1;
     constexpr int LDP = SPT + 1;       // padded LDS row
-    constexpr int NW = ana_nw(F32);
+    constexpr int NW = ana_nw(F32, SPIN != 0);
     constexpr int NT = 64 * NW;
     constexpr int CPJ = SPIN ? 4 : 2;  // columns per transform
     constexpr int NCOL = NCB * 16;
@@ -933,7 +933,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
 }
 
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64 * ana_nw(F32), 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
+__global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_anal(LegView v, const int *__restrict__ mlist,
                                                                   const double *__restrict__ phase,
                                                                   double *__restrict__ alm,
                                                                   int jobs_per_group, int mode)
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(64 * ana_nw(F32), 2) void k_legendre_anal(LegView v
 
 // Persistent form for a batch of plans (one queue, atomic counter).
 template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64 * ana_nw(F32), 2) void k_legendre_anal_batch(const LegView *__restrict__ views,
+__global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_anal_batch(const LegView *__restrict__ views,
                                                                         const BatchAnaItem *__restrict__ items,
                                                                         int nitems, BatchPtrs ptrs, int mode,
                                                                         unsigned *counter)
@@ -1002,7 +1002,7 @@ static void launch_anal_t(const Plan &p, const LegView &v, const double *phase, 
 {
     const int jpg = NCB * 16 / (SPIN ? 4 : 2);
     dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + jpg - 1) / jpg));
-    hipLaunchKernelGGL((k_legendre_anal<SPIN, NCB, F32>), grid, dim3(64 * ana_nw(F32)), 0, s, v,
+    hipLaunchKernelGGL((k_legendre_anal<SPIN, NCB, F32>), grid, dim3(64 * ana_nw(F32, SPIN != 0)), 0, s, v,
                        p.d_anal_ms, phase, alm, jpg, mode);
 }
 
@@ -1090,9 +1090,9 @@ template <int SPIN, int NCB, bool F32>
 static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     auto k = k_legendre_anal_batch<SPIN, NCB, F32>;
-    static const int groups = persistent_groups(k, 64 * ana_nw(F32));
+    static const int groups = persistent_groups(k, 64 * ana_nw(F32, SPIN != 0));
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
-    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * ana_nw(F32)), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
+    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * ana_nw(F32, SPIN != 0)), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
                        mode, b.d_counter);
 }
 

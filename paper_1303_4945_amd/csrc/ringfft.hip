@@ -107,6 +107,32 @@ __device__ __forceinline__ double2 cmul_mi(double2 a, bool fwd)
     return fwd ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
 }
 
+// Element loop n = threadIdx.x + j blockDim.x over [0, count), U elements
+// per thread at a time: get(n) for all of them first (their global loads in
+// flight together: one memory latency per U elements instead of one per
+// element), then put(n, value).  Indices past the end are clamped to
+// count - 1 rather than branched on, so the gets form straight-line code.
+// GUARD = false: put also runs for clamped indices (it must then be a plain
+// store of get's value, which the owner of count - 1 stores too); GUARD = true
+// (read-modify-write of shared data): put runs for n < count only.
+constexpr int LOOP_U = 4;
+template <bool GUARD, int U, typename Get, typename Put>
+__device__ __forceinline__ void batched_loop(int count, Get get, Put put)
+{
+    const int T = (int)blockDim.x;
+    for (int n0 = threadIdx.x; n0 < count; n0 += U * T) {
+        decltype(get(0)) v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = get(min(n0 + j * T, count - 1));
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int n = n0 + j * T;
+            if (!GUARD) put(min(n, count - 1), v[j]);
+            else if (n < count) put(n, v[j]);
+        }
+    }
+}
+
 // small DFT out_k = sum_j v_j w_r^{jk}, w_r = e^{-2 pi i / r} (fwd) or conjugate.
 template <int R>
 __device__ __forceinline__ void small_dft(double2 *v, bool fwd, const double2 *tw, int n)
@@ -544,17 +570,15 @@ __device__ __forceinline__ void bluestein(double2 *buf, const FftView &fv, const
     // chirp for sign s: w_n = e^{s i pi n^2/L}; table holds s = +
     auto wch = [&](int n) { double2 c = chirp[n]; return fwd ? cconj(c) : c; };
     const int M = d.M;
-    for (int n = threadIdx.x; n < M; n += blockDim.x) {
-        double2 a = make_double2(0.0, 0.0);
-        if (n < L) a = cmul(buf[PADI(n)], wch(n));
-        buf[PADI(n)] = a;
-    }
+    auto put = [&](int n, double2 v) { buf[PADI(n)] = v; };
+    batched_loop<true, LOOP_U>(M, [&](int n) { return n < L ? cmul(buf[PADI(n)], wch(n)) : make_double2(0.0, 0.0); },
+                       put);
     __syncthreads();
     fft_dif<POW2>(buf, in, true, fv.ctab);
-    for (int p = threadIdx.x; p < M; p += blockDim.x) buf[PADI(p)] = cmul(buf[PADI(p)], bh[p]);
+    batched_loop<true, LOOP_U>(M, [&](int p) { return cmul(buf[PADI(p)], bh[p]); }, put);
     __syncthreads();
     fft_dit<POW2>(buf, in, false, fv.ctab);
-    for (int k = threadIdx.x; k < L; k += blockDim.x) buf[PADI(k)] = cmul(buf[PADI(k)], wch(k));
+    batched_loop<true, LOOP_U>(L, [&](int k) { return cmul(buf[PADI(k)], wch(k)); }, put);
     __syncthreads();
 }
 
@@ -629,6 +653,21 @@ __device__ __forceinline__ double2 fold_bin(const FftView &fv, const double2 *Fr
     return s;
 }
 
+// fold_bin for N > 2 mv, where bin k holds at most one term (m = k, or
+// m = N - k conjugated): no loops, so that the loads of several bins can be
+// issued together.
+__device__ __forceinline__ double2 fold_bin_single(const FftView &fv, const double2 *Frow, int y, int N, int mv,
+                                                   int k)
+{
+    const bool refl = k > mv;
+    const int m = refl ? N - k : k;
+    const bool ok = m <= mv;
+    const int mc = ok ? m : 0;
+    const double2 t = cmul(Frow[mc], ring_rot(fv, y, mc));
+    const double2 z = refl ? cconj(t) : t;
+    return ok ? z : make_double2(0.0, 0.0);
+}
+
 // Rader's algorithm for a prime length L with smooth L-1: with a generator g
 // of the multiplicative group mod L, a_p = x_{g^p} and b_q = w^{g^{-q}}
 // (w = e^{-+2 pi i / L}), X_{g^{-q}} = x_0 + (a (*) b)_q, a cyclic convolution of
@@ -667,7 +706,8 @@ __device__ __forceinline__ RaderEnds rader(double2 *buf, const FftView &fv, cons
     fft_dif<POW2>(buf, in, true, fv.ctab);
     const double2 A0 = buf[PADI(0)];        // DC of the reordered input: sum_{n>0} x_n
     __syncthreads();
-    for (int p = threadIdx.x; p < Lm; p += blockDim.x) buf[PADI(p)] = cmul(buf[PADI(p)], bh[p]);
+    batched_loop<true, LOOP_U>(Lm, [&](int p) { return cmul(buf[PADI(p)], bh[p]); },
+                       [&](int p, double2 v) { buf[PADI(p)] = v; });
     __syncthreads();
     fft_dit<POW2>(buf, in, false, fv.ctab);
     return RaderEnds{x0, cadd(x0, A0)};
@@ -683,8 +723,8 @@ struct SpecRead {
     __device__ __forceinline__ double2 operator()(int k) const
     {
         if constexpr (MODE == KMODE_RADER) {
-            if (k == 0) return X0;
-            return cadd(x0, buf[PADI(qpos[k])]);
+            const double2 v = cadd(x0, buf[PADI(qpos[k])]);   // qpos[0] exists (unused)
+            return k == 0 ? X0 : v;
         } else {
             return buf[PADI(pos ? pos[k] : k)];
         }
@@ -703,7 +743,7 @@ __device__ __forceinline__ SpecRead<MODE> ring_transform(double2 *buf, const Fft
     if constexpr (MODE == KMODE_SPLIT) {
         bluestein_split<FFT_NREG, POW2>(buf, fv, d, fwd, load);
     } else if constexpr (MODE == KMODE_RADER) {
-        for (int n = threadIdx.x; n < L; n += blockDim.x) buf[PADI(n)] = load(n);
+        batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[PADI(n)] = v; });
         __syncthreads();
         const RaderEnds e = rader<POW2>(buf, fv, d, fwd);
         r.x0 = e.x0;
@@ -714,11 +754,11 @@ __device__ __forceinline__ SpecRead<MODE> ring_transform(double2 *buf, const Fft
         if (direct && !fwd) {
             // inverse: spectrum in at digit-reversed positions, signal out natural
             const int *pos = fv.itab + in.pos;
-            for (int n = threadIdx.x; n < L; n += blockDim.x) buf[PADI(pos[n])] = load(n);
+            batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[PADI(pos[n])] = v; });
             __syncthreads();
             fft_dit<POW2>(buf, in, false, fv.ctab);
         } else {
-            for (int n = threadIdx.x; n < L; n += blockDim.x) buf[PADI(n)] = load(n);
+            batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[PADI(n)] = v; });
             __syncthreads();
             if (direct) {
                 fft_dif<POW2>(buf, in, true, fv.ctab);
@@ -762,29 +802,48 @@ __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__re
             if (Fb) B = fold_bin(fv, Fb, row.yb, N, mvb, k);
             return make_double2(A.x - B.y, A.y + B.x);   // A + iB
         };
-        const SpecRead<MODE> out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
-        for (int x = threadIdx.x; x < N; x += blockDim.x) {
-            const double2 z = out(x);
-            mp[fv.ofs[row.ya] + (int64_t)x * fv.stride] = wa * z.x;
-            if (row.yb >= 0) mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] = wb * z.y;
-        }
+        // no aliasing: one term per bin; a missing second ring reads ring a's
+        // row with mv = -1 (no term)
+        const double2 *Fbs = Fb ? Fb : Fa;
+        const int ybs = Fb ? row.yb : row.ya;
+        auto zin1 = [&](int k) {
+            const double2 A = fold_bin_single(fv, Fa, row.ya, N, mva, k);
+            const double2 B = fold_bin_single(fv, Fbs, ybs, N, mvb, k);
+            return make_double2(A.x - B.y, A.y + B.x);
+        };
+        SpecRead<MODE> out;
+        if (N > 2 * max(mva, mvb)) out = ring_transform<MODE, POW2>(buf, fv, d, false, zin1);
+        else out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
+        const int64_t oa = fv.ofs[row.ya], ob = row.yb >= 0 ? fv.ofs[row.yb] : oa;
+        const bool hasb = row.yb >= 0;
+        batched_loop<false, LOOP_U>(N, out, [&](int x, double2 z) {
+            mp[oa + (int64_t)x * fv.stride] = wa * z.x;
+            if (hasb) mp[ob + (int64_t)x * fv.stride] = wb * z.y;
+        });
     } else {
         // even N = 2h: Z_k = X_k (1 + i w^k) + conj(X_{h-k}) (1 - i w^k), w = e^{2 pi i/N}
         const int h = N / 2;
         const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}
-        auto zin = [&](int k) {
-            double2 X = fold_bin(fv, Fa, row.ya, N, mva, k);
-            double2 Y = cconj(fold_bin(fv, Fa, row.ya, N, mva, h - k));
+        auto pack = [&](double2 X, double2 Y, int k) {
             double2 w = cconj(htw[k]);
             double2 iw = make_double2(-w.y, w.x);
             return cadd(cadd(X, cmul(X, iw)), csub(Y, cmul(Y, iw)));
         };
-        const SpecRead<MODE> out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
-        for (int n = threadIdx.x; n < h; n += blockDim.x) {
-            const double2 z = out(n);
-            mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride] = wa * z.x;
-            mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride] = wa * z.y;
-        }
+        auto zin = [&](int k) {
+            return pack(fold_bin(fv, Fa, row.ya, N, mva, k), cconj(fold_bin(fv, Fa, row.ya, N, mva, h - k)), k);
+        };
+        auto zin1 = [&](int k) {
+            return pack(fold_bin_single(fv, Fa, row.ya, N, mva, k),
+                        cconj(fold_bin_single(fv, Fa, row.ya, N, mva, h - k)), k);
+        };
+        SpecRead<MODE> out;
+        if (N > 2 * mva) out = ring_transform<MODE, POW2>(buf, fv, d, false, zin1);
+        else out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
+        const int64_t oa = fv.ofs[row.ya];
+        batched_loop<false, LOOP_U>(h, out, [&](int n, double2 z) {
+            mp[oa + (int64_t)(2 * n) * fv.stride] = wa * z.x;
+            mp[oa + (int64_t)(2 * n + 1) * fv.stride] = wa * z.y;
+        });
     }
 }
 
@@ -813,21 +872,18 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             const int mv = min(fv.mvalid[y], fv.mmax);
             const double w = use_weights ? fv.weight[y] : 1.0;
             double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
-            for (int m = threadIdx.x; m <= mv; m += blockDim.x) {
+            batched_loop<false, LOOP_U>(mv + 1, [&](int m) {
                 const int k = m % N;
                 const int kc = (N - k) % N;
                 const double2 Zk = rd(k), Zc = cconj(rd(kc));
-                double2 S;
-                if (!side) S = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
-                else {
-                    // (Zk - Zc) / (2i)
-                    const double2 dd = csub(Zk, Zc);
-                    S = make_double2(0.5 * dd.y, -0.5 * dd.x);
-                }
+                // side 0: (Zk + Zc) / 2; side 1: (Zk - Zc) / (2i)
+                const double2 dd = csub(Zk, Zc);
+                const double2 S = side ? make_double2(0.5 * dd.y, -0.5 * dd.x)
+                                       : make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
                 const double2 r = cconj(ring_rot(fv, y, m));
                 const double2 g = cmul(S, r);
-                G[m] = make_double2(w * g.x, w * g.y);
-            }
+                return make_double2(w * g.x, w * g.y);
+            }, [&](int m, double2 g) { G[m] = g; });
         }
     } else {
         const int h = N / 2;
@@ -842,25 +898,24 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
         const int mv = min(fv.mvalid[y], fv.mmax);
         const double w = use_weights ? fv.weight[y] : 1.0;
         double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
-        for (int m = threadIdx.x; m <= mv; m += blockDim.x) {
+        batched_loop<false, LOOP_U>(mv + 1, [&](int m) {
             int k = m % N;
-            bool cj = false;
-            if (k > h) { k = N - k; cj = true; }     // X_{N-k} = conj X_k
+            const bool cj = k > h;                   // X_{N-k} = conj X_k
+            if (cj) k = N - k;
             // X_k = E_k + e^{-2 pi i k/N} O_k, E/O from Z_k and conj Z_{h-k} (indices mod h)
             const int k1 = k % h, k2 = (h - k) % h;
             const double2 Zk = rd(k1), Zc = cconj(rd(k2));
             const double2 E = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
             const double2 dd = csub(Zk, Zc);
             const double2 O = make_double2(0.5 * dd.y, -0.5 * dd.x);
-            double2 tw;
-            if (k < h) tw = htw[k];
-            else tw = make_double2(-1.0, 0.0);     // k == h: e^{-i pi}
+            const double2 t = htw[k < h ? k : 0];
+            const double2 tw = k < h ? t : make_double2(-1.0, 0.0);   // k == h: e^{-i pi}
             double2 X = cadd(E, cmul(tw, O));
             if (cj) X = cconj(X);
             const double2 r = cconj(ring_rot(fv, y, m));
             const double2 g = cmul(X, r);
-            G[m] = make_double2(w * g.x, w * g.y);
-        }
+            return make_double2(w * g.x, w * g.y);
+        }, [&](int m, double2 g) { G[m] = g; });
     }
 }
 

@@ -37,10 +37,11 @@ struct SlotHost {
     double chalf = 0, shalf = 0;  // cos t/2, sin t/2
 };
 
-// wavefronts per analysis work group: eight in FP64 (half the passes over a_lm
-// of four; the LDS then holds one work group per CU), four in the FP32 form
-// (whose separate partial-sum buffers would not fit eight)
-constexpr int ana_nw(bool f32) { return f32 ? 4 : 8; }
+// wavefronts per analysis work group: eight for spin > 0 in FP64 (half the
+// passes over a_lm of four; the LDS then holds one work group per CU), four
+// for spin 0 (measured faster) and in the FP32 form (whose separate partial-sum
+// buffers would not fit eight)
+constexpr int ana_nw(bool f32, bool spin) { return (f32 || !spin) ? 4 : 8; }
 constexpr int NUM_XCD = 8;      // accelerator dies of the MI355X (work groups go round robin)
 
 // Synthesis work item of one wavefront: one m, one slot tile, one group of
