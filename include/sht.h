@@ -175,7 +175,9 @@ int sht_execute(sht_plan *p, int direction, const double *in, double *out,
    same Legendre step): in = a_lm, out = F phases; SHT_ALM2MAP_DERIV1: in =
    spin-0 a_lm, out = F phases of the derivative maps.
    SHT_MAP2ALM / SHT_ALM2MAP_ADJOINT / SHT_ALM2MAP_GRAD: in = G phases, out = a_lm
-   (GRAD also applies fac_m); the DERIV1 adjoints: out = one component. */
+   (GRAD also applies fac_m); the DERIV1 adjoints: out = one component.
+   Phase entries of (m, ring) terms that the polar criterion (Eqs. 7-8) drops
+   are returned as zero, here and from sht_ring_fft. */
 int sht_legendre(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 

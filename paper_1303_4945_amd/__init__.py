@@ -286,19 +286,19 @@ class Plan:
         """Gradient of a real loss with respect to the a_lm of alm2map_deriv1."""
         return self._run(_lib.sht_execute, ALM2MAP_DERIV1_GRAD, grad_maps, self.deriv_alm_shape, stream, out)
 
-    def legendre_synth(self, alm, stream=None):
-        return self._run(_lib.sht_legendre, ALM2MAP, alm, self.phase_shape, stream)
+    def legendre_synth(self, alm, stream=None, out=None):
+        return self._run(_lib.sht_legendre, ALM2MAP, alm, self.phase_shape, stream, out)
 
-    def legendre_anal(self, phases, stream=None):
-        return self._run(_lib.sht_legendre, MAP2ALM, phases, self.alm_shape, stream)
+    def legendre_anal(self, phases, stream=None, out=None):
+        return self._run(_lib.sht_legendre, MAP2ALM, phases, self.alm_shape, stream, out)
 
-    def ring_synth(self, phases, weights: bool = False, stream=None):
+    def ring_synth(self, phases, weights: bool = False, stream=None, out=None):
         d = MAP2ALM_ADJOINT if weights else ALM2MAP
-        return self._run(_lib.sht_ring_fft, d, phases, self.map_shape, stream)
+        return self._run(_lib.sht_ring_fft, d, phases, self.map_shape, stream, out)
 
-    def ring_anal(self, maps, weights: bool = True, stream=None):
+    def ring_anal(self, maps, weights: bool = True, stream=None, out=None):
         d = MAP2ALM if weights else ALM2MAP_ADJOINT
-        return self._run(_lib.sht_ring_fft, d, maps, self.phase_shape, stream)
+        return self._run(_lib.sht_ring_fft, d, maps, self.phase_shape, stream, out)
 
     def flops(self, direction=ALM2MAP):
         f, b = ctypes.c_double(), ctypes.c_double()

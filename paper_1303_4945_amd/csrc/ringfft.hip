@@ -1591,4 +1591,27 @@ int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_w
     return check_hip(hipGetLastError(), "ring analysis launch");
 }
 
+// Zeroes the phase entries above each ring's last kept m (the terms the polar
+// criterion drops; neither step writes them and the full transforms never read
+// them), so that the staged steps hand over fully defined phases.
+__global__ __launch_bounds__(256) void k_phase_tail_zero(double2 *phase, const int *mvalid, int nrings, int mmax,
+                                                         int ntc)
+{
+    const int y = blockIdx.x;
+    const int mv = min(mvalid[y], mmax);
+    for (int tc = 0; tc < ntc; ++tc) {
+        double2 *row = phase + ((int64_t)tc * nrings + y) * (mmax + 1);
+        for (int m = mv + 1 + (int)threadIdx.x; m <= mmax; m += blockDim.x) row[m] = make_double2(0.0, 0.0);
+    }
+}
+
+int launch_phase_tail_zero(const Plan &p, double *phase, hipStream_t s)
+{
+    const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
+    if (p.geom.nrings == 0) return SHT_OK;
+    hipLaunchKernelGGL(k_phase_tail_zero, dim3((unsigned)p.geom.nrings), dim3(256), 0, s,
+                       reinterpret_cast<double2 *>(phase), D->mvalid, p.geom.nrings, p.mmax, p.ntrans * p.ncomp);
+    return check_hip(hipGetLastError(), "phase tail launch");
+}
+
 }  // namespace sht

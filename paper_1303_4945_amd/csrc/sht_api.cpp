@@ -922,8 +922,12 @@ int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, false, true);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (synth_direction(direction)) rc = launch_legendre_synth(*p, in, out, deriv_direction(direction), s);
-    else rc = launch_legendre_anal(*p, in, out, anal_mode(direction), s);
+    if (synth_direction(direction)) {
+        rc = launch_legendre_synth(*p, in, out, deriv_direction(direction), s);
+        if (!rc) rc = launch_phase_tail_zero(*p, out, s);
+    } else {
+        rc = launch_legendre_anal(*p, in, out, anal_mode(direction), s);
+    }
     if (rc) return rc;
     return finish_launch("sht_legendre");
 }
@@ -935,8 +939,12 @@ int sht_ring_fft(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, true, false);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (synth_direction(direction)) rc = launch_ring_synth(*p, in, out, weighted_direction(direction), s);
-    else rc = launch_ring_anal(*p, in, out, weighted_direction(direction), s);
+    if (synth_direction(direction)) {
+        rc = launch_ring_synth(*p, in, out, weighted_direction(direction), s);
+    } else {
+        rc = launch_ring_anal(*p, in, out, weighted_direction(direction), s);
+        if (!rc) rc = launch_phase_tail_zero(*p, out, s);
+    }
     if (rc) return rc;
     return finish_launch("sht_ring_fft");
 }

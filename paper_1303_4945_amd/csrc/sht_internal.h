@@ -212,6 +212,7 @@ void fft_plan_free(FftPlan &f);
 int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_weights, hipStream_t s);
 int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights,
                      hipStream_t s);
+int launch_phase_tail_zero(const Plan &p, double *phase, hipStream_t s);
 
 // device memory helpers
 int dev_alloc(void **ptr, size_t bytes, const char *what);
