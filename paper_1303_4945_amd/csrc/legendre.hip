@@ -749,7 +749,8 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
     for (int t = 0; t < v.ntiles; ++t) ntiles_act += v.tile_mlim[t] >= m;
     int tcount = 0, tscan = 0;
     bool first = true;
-    const bool xneg = SPIN && ((i16 & 3) == 0 || (i16 & 3) == 3);
+    // column sign tau_o = (+, +, +, -) for o = 0..3 (see the stationary operand)
+    const bool tneg = SPIN && (i16 & 3) == 3;
     constexpr bool PSEP = AnaShared<SPIN, NCB, F32>::PSEP;
     int cidx = 0;   // chunks done (selects the partial-sum buffer)
     while (tcount < ntiles_act || first) {
@@ -770,8 +771,12 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
         // stationary phase fragments B[kk][j] for slot 4 ks + kk and column j + 16 cb:
         // gw[i][q] multiplies W (spin 2) or lambda (spin 0) rows of tile i; q = 0:
         // G_t + G_(pi-t), q = 1: G_t - G_(pi-t).  For output o the X rows take
-        // sigma_o times the W operand of column 3 - o, sigma = (-, +, +, -): formed
-        // when needed by a lane exchange within the four columns of a transform.
+        // sigma_o times the W operand of column 3 - o, sigma = (-, +, +, -).  The
+        // operand is stored times tau_o = (+, +, +, -) and the X rows take the
+        // column 3 - o of it by a lane exchange within the four columns of a
+        // transform, with no sign: the sums then hold tau_o (W_o + sigma_o X_o)
+        // (tau_o tau_(3-o) = sigma_o), and tau_o is applied once per chunk when
+        // they leave the registers.
         // (all loads unconditional from clamped addresses, so that they are
         // issued together rather than one conditional block at a time)
         T gw[TPW][2][KSA][NCB];
@@ -805,7 +810,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                     const double gs0 = phase[((rowbase + (ys >= 0 ? ys : 0)) * (v.mmax + 1) + m) * 2 + reim];
                     const double gn = (tok && yn >= 0) ? gn0 : 0.0;
                     const double gs = (tok && ys >= 0) ? ssign * gs0 : 0.0;
-                    const double sg = SPIN ? -1.0 : 1.0;
+                    const double sg = SPIN ? ((o == 3) ? 1.0 : -1.0) : 1.0;   // -tau_o (spin > 0)
                     gw[i][0][ks][cb] = (T)(sg * (gn + gs));
                     gw[i][1][ks][cb] = (T)(sg * (gn - gs));
                 }
@@ -873,7 +878,7 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                             for (int cb = 0; cb < NCB; ++cb) {
                                 acc[p][cb] = mfma(aw, gw[i][p][ks][cb], acc[p][cb]);
                                 const T q = quad_rev(gw[i][1 - p][ks][cb]);
-                                acc[p][cb] = mfma(ax, xneg ? -q : q, acc[p][cb]);
+                                acc[p][cb] = mfma(ax, q, acc[p][cb]);
                             }
                         }
                     }
@@ -903,10 +908,11 @@ __device__ __forceinline__ void anal_item(const LegView &v, const int m, const i
                         const int tl = col / CPJ, o = col % CPJ;
                         const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                         const int e = (((tl * NCOMP + comp) * LC) + p + 2 * row) * 2 + reim;
+                        const T a = tneg ? -acc[p][cb][r] : acc[p][cb][r];
                         if constexpr (PSEP)
-                            sh.psum[((cidx & 1) * NW + wave) * NOUTP + psidx(e)] = any_active ? (float)acc[p][cb][r] : 0.0f;
+                            sh.psum[((cidx & 1) * NW + wave) * NOUTP + psidx(e)] = any_active ? (float)a : 0.0f;
                         else
-                            part_w[psidx(e)] = any_active ? (double)acc[p][cb][r] : 0.0;
+                            part_w[psidx(e)] = any_active ? (double)a : 0.0;
                     }
             __syncthreads();
 #pragma unroll
