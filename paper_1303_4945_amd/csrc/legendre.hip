@@ -351,7 +351,13 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         const bool ok = t < v.ntrans && !(m == 0 && reim) && !(deriv && comp);
         bp[cb] = ok ? alm + (((int64_t)t * ncin + comp) * v.nalm + mbase) * 2 + reim : v.zeros;
     }
-    const bool xneg = SPIN && ((i16 & 3) == 1 || (i16 & 3) == 2);
+    // The X products need sigma_o = (+, -, -, +) times the coefficient of column
+    // 3 - o.  FP64: the staged coefficients carry tau_o = (+, +, -, +) instead
+    // (tau_o tau_(3-o) = sigma_o), taken by the lane exchange with no sign; the
+    // sums then hold tau_o times the result, undone once in the epilogue (FP32:
+    // measured slower, the exchanged operand is negated where sigma_o = -1).
+    const bool tneg = SPIN && !F32 && (i16 & 3) == 2;
+    const bool xneg = SPIN && F32 && ((i16 & 3) == 1 || (i16 & 3) == 2);
 
     // coefficients of a chunk: R[par][h][cb] = a(column, lc + 8h + 2kk + par),
     // loaded one chunk ahead from clamped addresses; degrees outside [l0, lmax]
@@ -407,7 +413,8 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int par = 0; par < 2; ++par) {
-                const double f = cfs[buf][0][8 * h + 2 * kk + par].w;
+                const double f0 = cfs[buf][0][8 * h + 2 * kk + par].w;
+                const double f = tneg ? -f0 : f0;
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) dst[par][h][cb] *= f;
             }
@@ -541,7 +548,7 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
             eys[sb][r] = v.slot_ys[slot];
         }
 
-    // epilogue: ring t = A0 + A1, ring pi - t = A0 - A1
+    // epilogue: ring t = A0 + A1, ring pi - t = sigma (A0 - A1), both times tau_o
 #pragma unroll
     for (int sb = 0; sb < NSB; ++sb)
 #pragma unroll
@@ -565,8 +572,9 @@ __device__ __forceinline__ void synth_item(const LegView &v, const WaveItem it,
                 const int comp = SPIN ? (o >> 1) : 0, reim = o & 1;
                 const int yn = eyn[sb][r], ys = eys[sb][r];
                 const int64_t rowbase = ((int64_t)t * NCOMP + comp) * v.nrings;
-                if (yn >= 0) phase[((rowbase + yn) * (v.mmax + 1) + m) * 2 + reim] = c0 + c1;
-                if (ys >= 0) phase[((rowbase + ys) * (v.mmax + 1) + m) * 2 + reim] = ssign * (c0 - c1);
+                const double ts = tneg ? -1.0 : 1.0;   // undo tau_o
+                if (yn >= 0) phase[((rowbase + yn) * (v.mmax + 1) + m) * 2 + reim] = ts * (c0 + c1);
+                if (ys >= 0) phase[((rowbase + ys) * (v.mmax + 1) + m) * 2 + reim] = (ssign * ts) * (c0 - c1);
             }
 }
 
