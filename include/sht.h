@@ -9,7 +9,10 @@
  *   analysis  (map2alm, Eq. 2):  a_lm = sum_y sum_x p_xy w_y lambda_lm(theta_y)
  *                                       exp(-i m phi0_y - 2 pi i m x / Nphi_y)
  *   adjoint synthesis (Sect. 4.5, Eq. 16 with W = 1): the analysis sums with
- *                                 every weight equal to one (Y^T).
+ *                                 every weight equal to one (Y^T);
+ *   adjoint analysis (Sect. 4.5):  W Y, the synthesis with every ring times w_y;
+ *   first-derivative maps (Sect. 4.3): df/dtheta and df/(sin theta dphi) of a
+ *                                 spin-0 field, as a spin-1 synthesis.
  *
  * Both are split into a Legendre step (Eqs. 4, 5: the phases F_{m,y}, G_{m,y})
  * and per-ring real FFTs (Eqs. 3, 6).  Every spin 0 <= s <= lmax is supported
