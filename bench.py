@@ -12,8 +12,9 @@ in HBM, run through the stage entry points so that per-kernel times can be
 taken with HIP events on the launch stream inside the timed region.  The
 staged Legendre synthesis and FFT analysis also zero the phase entries of
 polar-skipped terms (about 0.7 ms each here), which sht_execute does not
-run: the reported rate slightly understates the full transforms.  The CPU baseline times the oracle on a bounded
-sample of the same workload on the host cores.
+run: the reported rate slightly understates the full transforms.  The CPU
+baseline times the oracle on a bounded sample of the same workload on the
+host cores.
 """
 from __future__ import annotations
 
