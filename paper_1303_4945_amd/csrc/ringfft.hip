@@ -91,7 +91,14 @@ struct FftView {
 
 // LDS index with one complex of padding every 8 elements: the strided
 // butterfly accesses of radix 2, 4 and 8 then fall into distinct bank groups.
-__device__ __forceinline__ int PADI(int i) { return i + (i >> 3); }
+// The Rader kernels of inner lengths that are not powers of two (their
+// butterflies mostly read consecutive elements) run unpadded: there the
+// padding only broke up contiguous accesses (PAD = false).
+template <bool PAD>
+__device__ __forceinline__ int padi(int i) { return PAD ? i + (i >> 3) : i; }
+template <int MODE, bool POW2>
+constexpr bool lds_pad() { return MODE != KMODE_RADER || POW2; }
+__device__ __forceinline__ int PADI(int i) { return padi<true>(i); }
 constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
@@ -213,7 +220,7 @@ __device__ __forceinline__ void apply_powers(double2 *v, double2 w)
 }
 
 // one pass over the block of length Lb split by radix R (stride Ln = Lb / R)
-template <int R, bool DIT>
+template <int R, bool DIT, bool PAD = true>
 __device__ __forceinline__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
 {
     const int Ln = Lb / R;
@@ -226,7 +233,7 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, 
         const int base = b * Lb + n1;
         double2 v[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = buf[PADI(base + j * Ln)];
+        for (int j = 0; j < R; ++j) v[j] = buf[padi<PAD>(base + j * Ln)];
         const double2 w = tw_base(tw, tstep * n1, fwd);
         if constexpr (DIT) {
             apply_powers<R>(v, w);
@@ -236,7 +243,7 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int n, int Lb, bool fwd, 
             apply_powers<R>(v, w);
         }
 #pragma unroll
-        for (int j = 0; j < R; ++j) buf[PADI(base + j * Ln)] = v[j];
+        for (int j = 0; j < R; ++j) buf[padi<PAD>(base + j * Ln)] = v[j];
     }
     __syncthreads();
 }
@@ -280,7 +287,7 @@ template <> struct OddRoots<13> {
 // A_k = v_0 + sum_j s_j cos(2 pi jk/R) and B_k = sum_j d_j sin(2 pi jk/R) (sine
 // sign flipped for the inverse).  Outputs go to LDS as soon as they are formed,
 // so no second register array is live.
-template <int R, bool DIT>
+template <int R, bool DIT, bool PAD = true>
 __device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
 {
     constexpr int H = (R - 1) / 2;
@@ -295,7 +302,7 @@ __device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool f
         const int base = b * Lb + n1;
         double2 v[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = buf[PADI(base + j * Ln)];
+        for (int j = 0; j < R; ++j) v[j] = buf[padi<PAD>(base + j * Ln)];
         const double2 w = tw_base(tw, tstep * n1, fwd);
         if constexpr (DIT) apply_powers<R>(v, w);
         // DIF: outputs k and R - k take w^k and w^(R-k), formed upwards from w
@@ -313,7 +320,7 @@ __device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool f
             v[R - j] = dj;
             sum0 = cadd(sum0, sj);
         }
-        buf[PADI(base)] = sum0;
+        buf[padi<PAD>(base)] = sum0;
 #pragma unroll
         for (int k = 1; k <= H; ++k) {
             double2 A = v0, B = make_double2(0.0, 0.0);
@@ -335,8 +342,8 @@ __device__ __forceinline__ void fft_pass_odd(double2 *buf, int n, int Lb, bool f
                 pk = cmul(pk, w);
                 qk = cmul(qk, wc);
             }
-            buf[PADI(base + k * Ln)] = ok;
-            buf[PADI(base + (R - k) * Ln)] = okr;
+            buf[padi<PAD>(base + k * Ln)] = ok;
+            buf[padi<PAD>(base + (R - k) * Ln)] = okr;
         }
     }
     __syncthreads();
@@ -422,7 +429,7 @@ __device__ __forceinline__ void dft_reg(double2 *v, bool fwd)
 // combine only among themselves, so the intermediate values stay in registers
 // and the data cross LDS once.  DIT runs the two passes in the reverse order
 // with the twiddles before each DFT.  Same results as fft_pass twice.
-template <int R1, int R2, bool DIT>
+template <int R1, int R2, bool DIT, bool PAD = true>
 __device__ __forceinline__ void fft_pass2(double2 *buf, int n, int Lb, bool fwd, const double2 *tw)
 {
     const int LnA = Lb / R1;
@@ -439,7 +446,7 @@ __device__ __forceinline__ void fft_pass2(double2 *buf, int n, int Lb, bool fwd,
 #pragma unroll
         for (int j = 0; j < R1; ++j)
 #pragma unroll
-            for (int jb = 0; jb < R2; ++jb) v[j * R2 + jb] = buf[PADI(base + j * LnA + jb * LnB)];
+            for (int jb = 0; jb < R2; ++jb) v[j * R2 + jb] = buf[padi<PAD>(base + j * LnA + jb * LnB)];
         if constexpr (!DIT) {
 #pragma unroll
             for (int jb = 0; jb < R2; ++jb) {
@@ -468,26 +475,26 @@ __device__ __forceinline__ void fft_pass2(double2 *buf, int n, int Lb, bool fwd,
 #pragma unroll
         for (int k = 0; k < R1; ++k)
 #pragma unroll
-            for (int kb = 0; kb < R2; ++kb) buf[PADI(base + k * LnA + kb * LnB)] = v[k * R2 + kb];
+            for (int kb = 0; kb < R2; ++kb) buf[padi<PAD>(base + k * LnA + kb * LnB)] = v[k * R2 + kb];
     }
     __syncthreads();
 }
 
 // fused pairs that occur (the host orders each pair with R1 >= R2)
-template <bool DIT, bool POW2>
+template <bool DIT, bool POW2, bool PAD = true>
 __device__ __forceinline__ void fft_pass2_any(double2 *buf, int n, int Lb, int r1, int r2, bool fwd,
                                               const double2 *tw)
 {
     switch (r1 * 16 + r2) {
-    case 2 * 16 + 2: fft_pass2<2, 2, DIT>(buf, n, Lb, fwd, tw); break;
-    case 4 * 16 + 2: fft_pass2<4, 2, DIT>(buf, n, Lb, fwd, tw); break;
+    case 2 * 16 + 2: fft_pass2<2, 2, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+    case 4 * 16 + 2: fft_pass2<4, 2, DIT, PAD>(buf, n, Lb, fwd, tw); break;
     default:
         if constexpr (!POW2) {
             switch (r1 * 16 + r2) {
-            case 3 * 16 + 2: fft_pass2<3, 2, DIT>(buf, n, Lb, fwd, tw); break;
-            case 3 * 16 + 3: fft_pass2<3, 3, DIT>(buf, n, Lb, fwd, tw); break;
-            case 5 * 16 + 2: fft_pass2<5, 2, DIT>(buf, n, Lb, fwd, tw); break;
-            case 7 * 16 + 2: fft_pass2<7, 2, DIT>(buf, n, Lb, fwd, tw); break;
+            case 3 * 16 + 2: fft_pass2<3, 2, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 3 * 16 + 3: fft_pass2<3, 3, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 5 * 16 + 2: fft_pass2<5, 2, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 7 * 16 + 2: fft_pass2<7, 2, DIT, PAD>(buf, n, Lb, fwd, tw); break;
             default: break;
             }
         }
@@ -497,21 +504,21 @@ __device__ __forceinline__ void fft_pass2_any(double2 *buf, int n, int Lb, int r
 
 // POW2: only radices 2, 4, 8 occur (keeps the odd-radix code, and its
 // registers, out of the power-of-two kernels)
-template <bool DIT, bool POW2>
+template <bool DIT, bool POW2, bool PAD = true>
 __device__ __forceinline__ void fft_pass_any(double2 *buf, int n, int Lb, int r, bool fwd, const double2 *tw)
 {
     switch (r) {
-    case 2: fft_pass<2, DIT>(buf, n, Lb, fwd, tw); break;
-    case 4: fft_pass<4, DIT>(buf, n, Lb, fwd, tw); break;
-    case 8: fft_pass<8, DIT>(buf, n, Lb, fwd, tw); break;
+    case 2: fft_pass<2, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+    case 4: fft_pass<4, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+    case 8: fft_pass<8, DIT, PAD>(buf, n, Lb, fwd, tw); break;
     default:
         if constexpr (!POW2) {
             switch (r) {
-            case 3: fft_pass_odd<3, DIT>(buf, n, Lb, fwd, tw); break;
-            case 5: fft_pass_odd<5, DIT>(buf, n, Lb, fwd, tw); break;
-            case 7: fft_pass_odd<7, DIT>(buf, n, Lb, fwd, tw); break;
-            case 11: fft_pass_odd<11, DIT>(buf, n, Lb, fwd, tw); break;
-            case 13: fft_pass_odd<13, DIT>(buf, n, Lb, fwd, tw); break;
+            case 3: fft_pass_odd<3, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 5: fft_pass_odd<5, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 7: fft_pass_odd<7, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 11: fft_pass_odd<11, DIT, PAD>(buf, n, Lb, fwd, tw); break;
+            case 13: fft_pass_odd<13, DIT, PAD>(buf, n, Lb, fwd, tw); break;
             default: break;
             }
         }
@@ -520,18 +527,18 @@ __device__ __forceinline__ void fft_pass_any(double2 *buf, int n, int Lb, int r,
 }
 
 // natural order in, digit-reversed out
-template <bool POW2>
+template <bool POW2, bool PAD = true>
 __device__ __forceinline__ void fft_dif(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
 {
     const double2 *tw = ctab + in.tw;
     int Lb = in.n;
     for (int i = 0; i < in.nrad;) {
         if (in.fuse[i]) {
-            fft_pass2_any<false, POW2>(buf, in.n, Lb, in.rad[i], in.rad[i + 1], fwd, tw);
+            fft_pass2_any<false, POW2, PAD>(buf, in.n, Lb, in.rad[i], in.rad[i + 1], fwd, tw);
             Lb /= in.rad[i] * in.rad[i + 1];
             i += 2;
         } else {
-            fft_pass_any<false, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
+            fft_pass_any<false, POW2, PAD>(buf, in.n, Lb, in.rad[i], fwd, tw);
             Lb /= in.rad[i];
             i += 1;
         }
@@ -539,7 +546,7 @@ __device__ __forceinline__ void fft_dif(double2 *buf, const FftInner &in, bool f
 }
 
 // digit-reversed in, natural order out
-template <bool POW2>
+template <bool POW2, bool PAD = true>
 __device__ __forceinline__ void fft_dit(double2 *buf, const FftInner &in, bool fwd, const double2 *ctab)
 {
     const double2 *tw = ctab + in.tw;
@@ -547,11 +554,11 @@ __device__ __forceinline__ void fft_dit(double2 *buf, const FftInner &in, bool f
     for (int i = in.nrad - 1; i >= 0;) {
         if (i >= 1 && in.fuse[i - 1]) {
             Lb *= in.rad[i - 1] * in.rad[i];
-            fft_pass2_any<true, POW2>(buf, in.n, Lb, in.rad[i - 1], in.rad[i], fwd, tw);
+            fft_pass2_any<true, POW2, PAD>(buf, in.n, Lb, in.rad[i - 1], in.rad[i], fwd, tw);
             i -= 2;
         } else {
             Lb *= in.rad[i];
-            fft_pass_any<true, POW2>(buf, in.n, Lb, in.rad[i], fwd, tw);
+            fft_pass_any<true, POW2, PAD>(buf, in.n, Lb, in.rad[i], fwd, tw);
             i -= 1;
         }
     }
@@ -688,11 +695,11 @@ __device__ __forceinline__ RaderEnds rader(double2 *buf, const FftView &fv, cons
     // staged as separate real arrays: element-wise copies of double2 between
     // LDS and a private array keep the array out of registers
     double are[FFT_NREG], aim[FFT_NREG];
-    const double2 x0 = buf[PADI(0)];
+    const double2 x0 = buf[padi<POW2>(0)];
 #pragma unroll
     for (int j = 0; j < FFT_NREG; ++j) {
         const int p = threadIdx.x + j * blockDim.x;
-        const double2 t = buf[PADI(p < Lm ? gp[p] : 0)];
+        const double2 t = buf[padi<POW2>(p < Lm ? gp[p] : 0)];
         are[j] = t.x;
         aim[j] = t.y;
     }
@@ -700,21 +707,21 @@ __device__ __forceinline__ RaderEnds rader(double2 *buf, const FftView &fv, cons
 #pragma unroll
     for (int j = 0; j < FFT_NREG; ++j) {
         const int p = threadIdx.x + j * blockDim.x;
-        if (p < Lm) buf[PADI(p)] = make_double2(are[j], aim[j]);
+        if (p < Lm) buf[padi<POW2>(p)] = make_double2(are[j], aim[j]);
     }
     __syncthreads();
-    fft_dif<POW2>(buf, in, true, fv.ctab);
-    const double2 A0 = buf[PADI(0)];        // DC of the reordered input: sum_{n>0} x_n
+    fft_dif<POW2, POW2>(buf, in, true, fv.ctab);
+    const double2 A0 = buf[padi<POW2>(0)];        // DC of the reordered input: sum_{n>0} x_n
     __syncthreads();
-    batched_loop<true, LOOP_U>(Lm, [&](int p) { return cmul(buf[PADI(p)], bh[p]); },
-                       [&](int p, double2 v) { buf[PADI(p)] = v; });
+    batched_loop<true, LOOP_U>(Lm, [&](int p) { return cmul(buf[padi<POW2>(p)], bh[p]); },
+                       [&](int p, double2 v) { buf[padi<POW2>(p)] = v; });
     __syncthreads();
-    fft_dit<POW2>(buf, in, false, fv.ctab);
+    fft_dit<POW2, POW2>(buf, in, false, fv.ctab);
     return RaderEnds{x0, cadd(x0, A0)};
 }
 
 // Spectrum bin k (k < L) of a length-L transform finished in LDS by the mode.
-template <int MODE>
+template <int MODE, bool PAD>
 struct SpecRead {
     const double2 *buf;
     const int *pos;      // LDS mode, direct kind: digit-reversed position; else null
@@ -723,10 +730,10 @@ struct SpecRead {
     __device__ __forceinline__ double2 operator()(int k) const
     {
         if constexpr (MODE == KMODE_RADER) {
-            const double2 v = cadd(x0, buf[PADI(qpos[k])]);   // qpos[0] exists (unused)
+            const double2 v = cadd(x0, buf[padi<PAD>(qpos[k])]);   // qpos[0] exists (unused)
             return k == 0 ? X0 : v;
         } else {
-            return buf[PADI(pos ? pos[k] : k)];
+            return buf[padi<PAD>(pos ? pos[k] : k)];
         }
     }
 };
@@ -734,16 +741,16 @@ struct SpecRead {
 // Runs the length-L transform of the row in LDS.  load(n), n < L, gives the
 // input.  Returns the reader of the result in natural frequency order.
 template <int MODE, bool POW2, typename Load>
-__device__ __forceinline__ SpecRead<MODE> ring_transform(double2 *buf, const FftView &fv,
+__device__ __forceinline__ SpecRead<MODE, lds_pad<MODE, POW2>()> ring_transform(double2 *buf, const FftView &fv,
                                                          const FftLen &d, bool fwd, Load load)
 {
     const FftInner &in = fv.inner[d.inner];
     const int L = d.L;
-    SpecRead<MODE> r{buf, nullptr, nullptr, make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    SpecRead<MODE, lds_pad<MODE, POW2>()> r{buf, nullptr, nullptr, make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
     if constexpr (MODE == KMODE_SPLIT) {
         bluestein_split<FFT_NREG, POW2>(buf, fv, d, fwd, load);
     } else if constexpr (MODE == KMODE_RADER) {
-        batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[PADI(n)] = v; });
+        batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[padi<POW2>(n)] = v; });
         __syncthreads();
         const RaderEnds e = rader<POW2>(buf, fv, d, fwd);
         r.x0 = e.x0;
@@ -811,7 +818,7 @@ __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__re
             const double2 B = fold_bin_single(fv, Fbs, ybs, N, mvb, k);
             return make_double2(A.x - B.y, A.y + B.x);
         };
-        SpecRead<MODE> out;
+        SpecRead<MODE, lds_pad<MODE, POW2>()> out;
         if (N > 2 * max(mva, mvb)) out = ring_transform<MODE, POW2>(buf, fv, d, false, zin1);
         else out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
         const int64_t oa = fv.ofs[row.ya], ob = row.yb >= 0 ? fv.ofs[row.yb] : oa;
@@ -836,7 +843,7 @@ __global__ __launch_bounds__(1024) void k_ring_synth(FftView fv, const int *__re
             return pack(fold_bin_single(fv, Fa, row.ya, N, mva, k),
                         cconj(fold_bin_single(fv, Fa, row.ya, N, mva, h - k)), k);
         };
-        SpecRead<MODE> out;
+        SpecRead<MODE, lds_pad<MODE, POW2>()> out;
         if (N > 2 * mva) out = ring_transform<MODE, POW2>(buf, fv, d, false, zin1);
         else out = ring_transform<MODE, POW2>(buf, fv, d, false, zin);
         const int64_t oa = fv.ofs[row.ya];
@@ -866,7 +873,7 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             double b = row.yb >= 0 ? mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] : 0.0;
             return make_double2(a, b);
         };
-        const SpecRead<MODE> rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
+        const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
         for (int side = 0; side < (row.yb >= 0 ? 2 : 1); ++side) {
             const int y = side ? row.yb : row.ya;
             const int mv = min(fv.mvalid[y], fv.mmax);
@@ -892,7 +899,7 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             double b = mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride];
             return make_double2(a, b);
         };
-        const SpecRead<MODE> rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
+        const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
         const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}, k < h
         const int y = row.ya;
         const int mv = min(fv.mvalid[y], fv.mmax);
