@@ -166,3 +166,53 @@ def deriv_adjoint(geom, lmax: int, mmax: int, maps: np.ndarray, ms=None):
     eb = adjoint_synthesis(geom, lmax, mmax, 1, maps, ms=ms)
     k = np.sqrt(_degrees(lmax, mmax) * (_degrees(lmax, mmax) + 1.0))
     return eb[:, :1] * k[None, None, :, None]
+
+
+# ---------------------------------------------------------------- real harmonics
+# Real spherical harmonics (Sect. 4.5 refers their definition to an external
+# appendix; this reading): R_l0 = Y_l0 and, for m > 0, R_lm = sqrt(2) Re Y_lm,
+# R_l,-m = sqrt(2) Im Y_lm.  A real field f = sum r_lm R_lm then has the complex
+# coefficients a_l0 = r_l0, a_lm = (r_lm - i r_l,-m) / sqrt(2) (m > 0), and
+# r_l,-m is stored in the slot of Im a_lm.
+
+def _m_of_index(lmax: int, mmax: int) -> np.ndarray:
+    return np.concatenate([np.full(lmax + 1 - m, m) for m in range(mmax + 1)])
+
+
+def real_to_complex(lmax: int, mmax: int, r: np.ndarray) -> np.ndarray:
+    """[.., nalm, 2] real-harmonic coefficients -> complex a_lm (same layout)."""
+    r = np.asarray(r, dtype=np.float64)
+    mpos = _m_of_index(lmax, mmax) > 0
+    a = np.zeros_like(r)
+    a[..., ~mpos, 0] = r[..., ~mpos, 0]
+    a[..., mpos, 0] = r[..., mpos, 0] / np.sqrt(2.0)
+    a[..., mpos, 1] = -r[..., mpos, 1] / np.sqrt(2.0)
+    return a
+
+
+def complex_to_real(lmax: int, mmax: int, a: np.ndarray) -> np.ndarray:
+    """Inverse of real_to_complex (Im a_l0 is dropped)."""
+    a = np.asarray(a, dtype=np.float64)
+    mpos = _m_of_index(lmax, mmax) > 0
+    r = np.zeros_like(a)
+    r[..., ~mpos, 0] = a[..., ~mpos, 0]
+    r[..., mpos, 0] = np.sqrt(2.0) * a[..., mpos, 0]
+    r[..., mpos, 1] = -np.sqrt(2.0) * a[..., mpos, 1]
+    return r
+
+
+def synthesis_real(geom, lmax: int, mmax: int, spin: int, r: np.ndarray, rings=None):
+    """Synthesis from real-harmonic coefficients."""
+    return synthesis(geom, lmax, mmax, spin, real_to_complex(lmax, mmax, r), rings=rings)
+
+
+def analysis_real(geom, lmax: int, mmax: int, spin: int, maps: np.ndarray, ms=None):
+    """Analysis returning real-harmonic coefficients."""
+    return complex_to_real(lmax, mmax, analysis(geom, lmax, mmax, spin, maps, ms=ms))
+
+
+def adjoint_synthesis_real(geom, lmax: int, mmax: int, spin: int, maps: np.ndarray, ms=None):
+    """Transpose of synthesis_real: the chain rule through real_to_complex turns
+    fac_m Y^T x into sqrt(2) (Re, -Im) of Y^T x for m > 0, i.e. complex_to_real
+    of the plain Y^T."""
+    return complex_to_real(lmax, mmax, adjoint_synthesis(geom, lmax, mmax, spin, maps, ms=ms))

@@ -522,3 +522,45 @@ def test_deriv_adjoint_dot_product():
     fac = np.where(ms == 0, 1.0, 2.0)
     rhs = float(np.sum(fac[None, None, :] * (a[..., 0] * dt[..., 0] + a[..., 1] * dt[..., 1])))
     assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+# ---------------------------------------------------------------- real harmonics (Sect. 4.5)
+
+def test_real_harmonics_closed_forms():
+    """R_11 = sqrt(2) Re Y_11 = -sqrt(3/4pi) sin(theta) cos(phi),
+    R_1,-1 = sqrt(2) Im Y_11 = -sqrt(3/4pi) sin(theta) sin(phi), R_10 = Y_10."""
+    theta = np.array([0.3, 1.2, 2.5])
+    nphi = 9
+    g = _rings_geometry(theta, nphi, 0.4)
+    th = np.repeat(theta, nphi)
+    ph = np.concatenate([0.4 + 2 * math.pi * np.arange(nphi) / nphi] * len(theta))
+    lmax = 2
+    c = math.sqrt(3 / (4 * math.pi))
+    for (l, m, slot), ref in [((1, 1, 0), -c * np.sin(th) * np.cos(ph)),
+                              ((1, 1, 1), -c * np.sin(th) * np.sin(ph)),
+                              ((1, 0, 0), c * np.cos(th))]:
+        r = np.zeros((1, 1, si.nalm(lmax, lmax), 2))
+        r[0, 0, si.alm_index(lmax, l, m), slot] = 1.0
+        f = oracle.synthesis_real(g, lmax, lmax, 0, r)[0, 0]
+        assert np.max(np.abs(f - ref)) < 1e-14, (l, m, slot)
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_real_harmonics_orthonormal_and_plain_adjoint(spin):
+    """Under exact Gauss-Legendre quadrature the real harmonics are orthonormal
+    (analysis_real inverts synthesis_real), and adjoint_synthesis_real is the
+    plain transpose: <Y r, x> = <r, Y^T x> with no m-dependent factors."""
+    lmax = 10
+    g = si.gauss_geometry(lmax + 1, 2 * lmax + 1, 0.2)
+    r = si.random_alm(lmax, lmax, 1, spin, spectrum="unit", tag=71)
+    ls, ms = si.lm_arrays(lmax, lmax)
+    r[:, :, ms == 0, 1] = 0.0       # no slot for r_l,-0
+    if spin:
+        r[:, :, ls < spin, :] = 0.0
+    back = oracle.analysis_real(g, lmax, lmax, spin, oracle.synthesis_real(g, lmax, lmax, spin, r))
+    assert np.max(np.abs(back - r)) < 1e-13
+    h = si.healpix_geometry(4)
+    x = si.random_map(h, 1, 2 if spin else 1, tag=72)
+    lhs = float(np.sum(oracle.synthesis_real(h, lmax, lmax, spin, r) * x))
+    rhs = float(np.sum(r * oracle.adjoint_synthesis_real(h, lmax, lmax, spin, x)))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
