@@ -88,7 +88,16 @@ typedef struct sht_plan_opts {
                               (default 256; valid 64..700) */
     int flush_chunks;      /* FP32_MFMA: FP32 partial sums are carried into FP64
                               after this many 16-degree chunks (default 4) */
-    int reserved[8];
+    int real_harmonics;    /* 1: coefficients in real spherical harmonics storage
+                              (Sect. 4.5): r_lm in the slot of Re a_lm and r_l,-m
+                              in the slot of Im a_lm (m > 0), with R_l0 = Y_l0,
+                              R_lm = sqrt(2) Re Y_lm, R_l,-m = sqrt(2) Im Y_lm, i.e.
+                              a_lm = (r_lm - i r_l,-m) / sqrt(2).  The transform is
+                              then a plain real-linear map: SHT_ALM2MAP_ADJOINT and
+                              SHT_ALM2MAP_GRAD both return its transpose (no fac_m),
+                              and the same holds for the DERIV1 directions.  Costs
+                              a workspace of the size of the coefficients. */
+    int reserved[7];
 } sht_plan_opts;
 
 /* ---- geometry (Sect. 2, Sect. 4.4) ---- */

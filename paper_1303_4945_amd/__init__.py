@@ -51,7 +51,7 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 class PlanOpts(ctypes.Structure):
     _fields_ = [("no_polar_skip", ctypes.c_int), ("polar_T", ctypes.c_double),
                 ("rescale_bits", ctypes.c_int), ("flush_chunks", ctypes.c_int),
-                ("reserved", ctypes.c_int * 8)]
+                ("real_harmonics", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
 
 def _sig(name, res, *args):
@@ -200,7 +200,7 @@ class Plan:
     def __init__(self, geom: Geometry, lmax: int, mmax: int | None = None, spin: int = 0,
                  ntrans: int = 1, precision: str | int = "fp64", polar: bool = True,
                  polar_T: float | None = None, rescale_bits: int | None = None,
-                 flush_chunks: int | None = None):
+                 flush_chunks: int | None = None, real_harmonics: bool = False):
         mmax = lmax if mmax is None else mmax
         if isinstance(precision, str):
             precision = {"fp64": FP64, "fp32_mfma": FP32_MFMA}[precision]
@@ -209,6 +209,7 @@ class Plan:
         o.polar_T = float(polar_T or 0.0)
         o.rescale_bits = int(rescale_bits or 0)
         o.flush_chunks = int(flush_chunks or 0)
+        o.real_harmonics = 1 if real_harmonics else 0
         h = _vp()
         _check(_lib.sht_plan_create(geom._h, lmax, mmax, spin, ntrans, precision, ctypes.byref(o),
                                     ctypes.byref(h)))

@@ -82,6 +82,12 @@ int batch_enqueue(Batch &b, int direction, const double *const *in, double *cons
         for (int i = 0; i < np; ++i) {
             ptrs.in[i] = in[i];
             ptrs.out[i] = b.plans[i]->d_phase;
+            if (b.real_h) {
+                if ((rc = launch_real_harm(*b.plans[i], in[i], b.plans[i]->d_rh,
+                                           deriv_direction(direction) ? 1 : b.plans[i]->ncomp, true, s)))
+                    return rc;
+                ptrs.in[i] = b.plans[i]->d_rh;
+            }
         }
         if ((rc = launch_legendre_synth_batch(b, ptrs, deriv_direction(direction), s))) return rc;
         for (int i = 0; i < np; ++i)
@@ -97,7 +103,12 @@ int batch_enqueue(Batch &b, int direction, const double *const *in, double *cons
             ptrs.in[i] = b.plans[i]->d_phase;
             ptrs.out[i] = out[i];
         }
-        if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction), s))) return rc;
+        if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction, b.real_h), s))) return rc;
+        if (b.real_h)
+            for (int i = 0; i < np; ++i)
+                if ((rc = launch_real_harm(*b.plans[i], out[i], out[i],
+                                           deriv_direction(direction) ? 1 : b.plans[i]->ncomp, false, s)))
+                    return rc;
     }
     return SHT_OK;
 }
@@ -183,9 +194,10 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
             set_error("plan %d is not a valid plan", i);
             return SHT_ESTATE;
         }
-        if (i > 0 && (p->spin != b->spin || p->precision != b->precision || p->device != b->plans[0]->device)) {
+        if (i > 0 && (p->spin != b->spin || p->precision != b->precision || p->device != b->plans[0]->device ||
+                      p->real_h != b->real_h)) {
             delete b;
-            set_error("all plans of a batch must have the same spin, precision and device");
+            set_error("all plans of a batch must have the same spin, precision, device and coefficient storage");
             return SHT_EINVAL;
         }
         for (Plan *q : b->plans)
@@ -196,6 +208,7 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
             }
         b->spin = p->spin;
         b->precision = p->precision;
+        b->real_h = p->real_h;
         maxj = std::max(maxj, p->ntrans);
         b->plans.push_back(p);
     }

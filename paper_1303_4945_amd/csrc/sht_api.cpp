@@ -406,6 +406,7 @@ static void plan_free_device(Plan *p)
     dev_free(p->d_tile_mlim); dev_free(p->d_synth_items); dev_free(p->d_anal_ms);
     dev_free(p->d_zeros);
     dev_free(p->d_dfac);
+    dev_free(p->d_rh);
     dev_free(p->d_phase);
     fft_plan_free(p->fft);
     p->d_slot_cos = p->d_slot_sin = p->d_slot_chalf = p->d_slot_shalf = nullptr;
@@ -414,6 +415,7 @@ static void plan_free_device(Plan *p)
     p->d_tile_mlim = nullptr; p->d_synth_items = nullptr; p->d_anal_ms = nullptr;
     p->d_zeros = nullptr;
     p->d_dfac = nullptr;
+    p->d_rh = nullptr;
     p->d_phase = nullptr;
 }
 
@@ -748,6 +750,9 @@ static int plan_build(Plan &p)
 
     p.phase_elems = (int64_t)p.ntrans * p.ncomp * p.geom.nrings * (p.mmax + 1);
     if ((rc = dev_alloc((void **)&p.d_phase, (size_t)p.phase_elems * 16, "phase workspace"))) return rc;
+    if (p.real_h &&
+        (rc = dev_alloc((void **)&p.d_rh, (size_t)p.ntrans * p.ncomp * p.nalm * 16, "real harmonics workspace")))
+        return rc;
 
     if ((rc = fft_plan_build(p))) return rc;
     count_work(p);
@@ -876,6 +881,7 @@ int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans,
     p->polar_T = o.no_polar_skip ? -1.0 : (o.polar_T > 0 ? o.polar_T : std::max(100.0, 0.01 * lmax));
     p->rescale_bits = o.rescale_bits ? o.rescale_bits : 256;
     p->flush_chunks = o.flush_chunks ? o.flush_chunks : 4;
+    p->real_h = o.real_harmonics != 0;
     p->nalm = sht_nalm(lmax, mmax);
     int rc = plan_build(*p);
     if (rc) {
@@ -905,12 +911,19 @@ int sht_execute(sht_plan *h, int direction, const double *in, double *out, void 
     int rc = check_exec_args(p, direction, in, out, false, false);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
+    const int acomp = deriv_direction(direction) ? 1 : p->ncomp;
     if (synth_direction(direction)) {
-        if ((rc = launch_legendre_synth(*p, in, p->d_phase, deriv_direction(direction), s))) return rc;
+        const double *a = in;
+        if (p->real_h) {
+            if ((rc = launch_real_harm(*p, in, p->d_rh, acomp, true, s))) return rc;
+            a = p->d_rh;
+        }
+        if ((rc = launch_legendre_synth(*p, a, p->d_phase, deriv_direction(direction), s))) return rc;
         if ((rc = launch_ring_synth(*p, p->d_phase, out, weighted_direction(direction), s))) return rc;
     } else {
         if ((rc = launch_ring_anal(*p, in, p->d_phase, weighted_direction(direction), s))) return rc;
-        if ((rc = launch_legendre_anal(*p, p->d_phase, out, anal_mode(direction), s))) return rc;
+        if ((rc = launch_legendre_anal(*p, p->d_phase, out, anal_mode(direction, p->real_h), s))) return rc;
+        if (p->real_h && (rc = launch_real_harm(*p, out, out, acomp, false, s))) return rc;
     }
     return finish_launch("sht_execute");
 }
@@ -922,11 +935,18 @@ int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void
     int rc = check_exec_args(p, direction, in, out, false, true);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
+    const int acomp = deriv_direction(direction) ? 1 : p->ncomp;
     if (synth_direction(direction)) {
-        rc = launch_legendre_synth(*p, in, out, deriv_direction(direction), s);
+        const double *a = in;
+        if (p->real_h) {
+            rc = launch_real_harm(*p, in, p->d_rh, acomp, true, s);
+            a = p->d_rh;
+        }
+        if (!rc) rc = launch_legendre_synth(*p, a, out, deriv_direction(direction), s);
         if (!rc) rc = launch_phase_tail_zero(*p, out, s);
     } else {
-        rc = launch_legendre_anal(*p, in, out, anal_mode(direction), s);
+        rc = launch_legendre_anal(*p, in, out, anal_mode(direction, p->real_h), s);
+        if (!rc && p->real_h) rc = launch_real_harm(*p, out, out, acomp, false, s);
     }
     if (rc) return rc;
     return finish_launch("sht_legendre");

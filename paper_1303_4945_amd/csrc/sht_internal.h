@@ -115,6 +115,8 @@ struct Plan {
     double polar_T = 100.0;
     int rescale_bits = 256;
     int flush_chunks = 4;
+    bool real_h = false;             // real spherical harmonics storage
+    double *d_rh = nullptr;          // its conversion workspace (coefficients)
     int64_t nalm = 0;
     // slots
     std::vector<SlotHost> slots;
@@ -167,9 +169,10 @@ inline bool weighted_direction(int d) { return d == SHT_MAP2ALM || d == SHT_MAP2
 // analysis kernel mode bits
 constexpr int ANA_MODE_GRAD = 1;    // real-field gradient factor fac_m
 constexpr int ANA_MODE_DERIV = 2;   // adjoint of the derivative synthesis
-inline int anal_mode(int d)
+// (real spherical harmonics: no fac_m, the gradient is the plain transpose)
+inline int anal_mode(int d, bool real_h)
 {
-    return ((d == SHT_ALM2MAP_GRAD || d == SHT_ALM2MAP_DERIV1_GRAD) ? ANA_MODE_GRAD : 0) |
+    return ((!real_h && (d == SHT_ALM2MAP_GRAD || d == SHT_ALM2MAP_DERIV1_GRAD)) ? ANA_MODE_GRAD : 0) |
            (deriv_direction(d) ? ANA_MODE_DERIV : 0);
 }
 
@@ -182,6 +185,7 @@ struct Batch {
     uint32_t magic = kBatchMagic;
     std::vector<Plan *> plans;
     int spin = 0, precision = 0, syn_ncb = 1, ana_ncb = 1;
+    bool real_h = false;
     int nsyn = 0, nana = 0;
     LegView *d_views = nullptr;
     BatchSynItem *d_syn = nullptr;
@@ -213,6 +217,9 @@ int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_
 int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights,
                      hipStream_t s);
 int launch_phase_tail_zero(const Plan &p, double *phase, hipStream_t s);
+
+// real spherical harmonics storage <-> complex a_lm (realharm.hip)
+int launch_real_harm(const Plan &p, const double *in, double *out, int ncomp, bool to_complex, hipStream_t s);
 
 // device memory helpers
 int dev_alloc(void **ptr, size_t bytes, const char *what);
