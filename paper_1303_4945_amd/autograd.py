@@ -5,7 +5,8 @@ The backward pass is the library's adjoint synthesis Y^T (Sect. 4.5 of the
 paper: analysis with unit weights), with the real-field factor fac_m
 (1 for m = 0, 2 for m > 0) applied in the same kernel, so that for a real
 loss L the gradient tensor holds dL/dRe(a_lm) and dL/dIm(a_lm) in the
-(re, im) slots of the stored coefficients.
+(re, im) slots of the stored coefficients.  For a plan in real spherical
+harmonics storage the backward is the plain transpose (dL/dr in every slot).
 """
 from __future__ import annotations
 
