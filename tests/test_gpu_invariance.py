@@ -94,6 +94,8 @@ def test_gl4095_spin2_workload_sampled():
     p32 = sht.Plan(geom, lmax, spin=2, ntrans=16, precision="fp32_mfma")
     mp32 = to_host(p32.alm2map(d_a))
     assert rel_err(mp32, mp_h) < 1e-6
+    back32 = to_host(p32.map2alm(to_dev(mp_h)))
+    assert rel_err(back32, back) < 1e-6
 
 
 def test_healpix1024_workload_sampled():
