@@ -109,3 +109,24 @@ def test_no_device_reports_edevice():
     with pytest.raises(sht.ShtError) as e:
         sht.Plan(g, 7)
     assert e.value.status == sht.SHT_EDEVICE
+
+
+def test_plan_opts_layout_matches_header(tmp_path):
+    """The ctypes mirror of sht_plan_opts has the C layout of include/sht.h."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    sht = _sht()
+    fields = [f for f, _ in sht.PlanOpts._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"sht.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(sht_plan_opts));\n"
+                   + "".join(f"  printf(\"%zu\\n\", offsetof(sht_plan_opts, {f}));\n" for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == ctypes.sizeof(sht.PlanOpts)
+    assert out[1:] == [getattr(sht.PlanOpts, f).offset for f in fields]
