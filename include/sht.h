@@ -213,9 +213,11 @@ int sht_plan_info(const sht_plan *p, int64_t *n_legendre_items, int64_t *workspa
 
 /* ---- batches of plans (mixed band limits and grids) ---- */
 
-/* A batch runs several plans (same spin and direction per call) as one
-   stream-ordered unit: the Legendre work of every plan is merged into one
-   cost-ordered persistent launch, the ring FFTs into one launch.  The plans
+/* A batch runs several plans (same spin, precision and coefficient storage;
+   one direction per call) as one stream-ordered unit: the Legendre analyses of
+   every plan are merged into one cost-ordered persistent launch, the Legendre
+   syntheses and the ring FFTs run plan by plan, and on a non-null stream the
+   whole sequence is captured once into a HIP graph and replayed.  The plans
    are borrowed and must outlive the batch. */
 int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out);
 int sht_batch_execute(sht_batch *b, int direction, const double *const *in,

@@ -1,6 +1,6 @@
-// Batches of plans (one persistent Legendre launch over all plans, the ring
-// FFTs of every plan, optionally replayed from a captured HIP graph) and the
-// synthesis tile autotuner.
+// Batches of plans (one persistent Legendre analysis launch over all plans,
+// each plan's Legendre synthesis and ring FFTs, optionally replayed from a
+// captured HIP graph) and the synthesis tile autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,31 +23,8 @@ void batch_free(Batch *b)
     for (int d = 0; d < NUM_DIRECTIONS; ++d)
         if (b->graph[d]) (void)hipGraphExecDestroy(b->graph[d]);
     dev_free(b->d_views);
-    dev_free(b->d_syn);
     dev_free(b->d_ana);
     dev_free(b->d_counter);
-}
-
-// Queue of synthesis items of all plans, largest degree range first.
-void synth_queue(const Batch &b, std::vector<BatchSynItem> &q)
-{
-    const int cpj = b.spin ? 4 : 2;
-    const int jpg = b.syn_ncb * 16 / cpj;
-    std::vector<std::pair<int, BatchSynItem>> v;
-    for (int pi = 0; pi < (int)b.plans.size(); ++pi) {
-        const Plan &p = *b.plans[pi];
-        for (int m = 0; m <= p.mmax; ++m) {
-            const int cost = p.lmax + 1 - std::max(m, p.spin);
-            for (int t = 0; t < p.ntiles; ++t) {
-                if (p.tile_mlim[t] < m) continue;
-                for (int t0 = 0; t0 < p.ntrans; t0 += jpg)
-                    v.push_back({cost, BatchSynItem{pi, WaveItem{m, t, t0, 0}}});
-            }
-        }
-    }
-    std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
-    q.clear();
-    for (auto &e : v) q.push_back(e.second);
 }
 
 // Queue of analysis items (m, transform group) of all plans, by cost.
@@ -79,17 +56,19 @@ int batch_enqueue(Batch &b, int direction, const double *const *in, double *cons
     const int np = (int)b.plans.size();
     int rc;
     if (synth_direction(direction)) {
+        // each plan's own die-aware item list (its a_lm rows and phase lines stay
+        // in one L2; one cost-ordered queue over all plans measured slower)
         for (int i = 0; i < np; ++i) {
-            ptrs.in[i] = in[i];
-            ptrs.out[i] = b.plans[i]->d_phase;
+            const double *a = in[i];
             if (b.real_h) {
                 if ((rc = launch_real_harm(*b.plans[i], in[i], b.plans[i]->d_rh,
                                            deriv_direction(direction) ? 1 : b.plans[i]->ncomp, true, s)))
                     return rc;
-                ptrs.in[i] = b.plans[i]->d_rh;
+                a = b.plans[i]->d_rh;
             }
+            if ((rc = launch_legendre_synth(*b.plans[i], a, b.plans[i]->d_phase, deriv_direction(direction), s)))
+                return rc;
         }
-        if ((rc = launch_legendre_synth_batch(b, ptrs, deriv_direction(direction), s))) return rc;
         for (int i = 0; i < np; ++i)
             if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i],
                                         weighted_direction(direction), s)))
@@ -212,28 +191,22 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
         maxj = std::max(maxj, p->ntrans);
         b->plans.push_back(p);
     }
-    b->syn_ncb = synth_ncb_default(b->spin, maxj, b->precision);
     b->ana_ncb = anal_ncb(b->spin, maxj);
-    std::vector<BatchSynItem> sq;
     std::vector<BatchAnaItem> aq;
-    synth_queue(*b, sq);
     anal_queue(*b, aq);
     std::vector<LegView> views;
     for (Plan *p : b->plans) views.push_back(make_leg_view(*p));
-    b->nsyn = (int)sq.size();
     b->nana = (int)aq.size();
     int rc;
     if ((rc = dev_alloc((void **)&b->d_views, views.size() * sizeof(LegView), "batch tables")) ||
         (rc = dev_upload(b->d_views, views.data(), views.size() * sizeof(LegView), "batch tables")) ||
-        (rc = dev_alloc((void **)&b->d_syn, std::max<size_t>(1, sq.size()) * sizeof(BatchSynItem), "batch tables")) ||
         (rc = dev_alloc((void **)&b->d_ana, std::max<size_t>(1, aq.size()) * sizeof(BatchAnaItem), "batch tables")) ||
         (rc = dev_alloc((void **)&b->d_counter, 64, "batch counter"))) {
         batch_free(b);
         delete b;
         return rc;
     }
-    if ((!sq.empty() && (rc = dev_upload(b->d_syn, sq.data(), sq.size() * sizeof(BatchSynItem), "batch tables"))) ||
-        (!aq.empty() && (rc = dev_upload(b->d_ana, aq.data(), aq.size() * sizeof(BatchAnaItem), "batch tables")))) {
+    if (!aq.empty() && (rc = dev_upload(b->d_ana, aq.data(), aq.size() * sizeof(BatchAnaItem), "batch tables"))) {
         batch_free(b);
         delete b;
         return rc;

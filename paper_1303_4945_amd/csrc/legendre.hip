@@ -587,27 +587,6 @@ __global__ __launch_bounds__(64) void k_legendre_synth(LegView v, const WaveItem
     synth_item<SPIN, NCB, F32>(v, items[blockIdx.x], alm, phase, flush_chunks, deriv, sh);
 }
 
-// Persistent form for a batch of plans: every wavefront takes items from one
-// queue (ordered by cost) with an atomic counter until the queue is empty.
-template <int SPIN, int NCB, bool F32>
-__global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__restrict__ views,
-                                                             const BatchSynItem *__restrict__ items,
-                                                             int nitems, BatchPtrs ptrs, int flush_chunks,
-                                                             int deriv, unsigned *counter)
-{
-    __shared__ SynShared<SPIN, F32> sh;
-    for (;;) {
-        unsigned idx = 0;
-        if (threadIdx.x == 0) idx = atomicAdd(counter, 1u);
-        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0));
-        if (idx >= (unsigned)nitems) break;
-        const BatchSynItem bi = items[idx];
-        synth_item<SPIN, NCB, F32>(views[bi.plan], bi.it, ptrs.in[bi.plan], ptrs.out[bi.plan], flush_chunks,
-                                   deriv, sh);
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- analysis
 
 constexpr int ANA_LC = 32;   // degrees per chunk (16 per parity class)
@@ -1091,16 +1070,6 @@ static int persistent_groups(K kernel, int threads)
 }
 
 template <int SPIN, int NCB, bool F32>
-static void launch_synth_batch_t(const Batch &b, const BatchPtrs &ptrs, int deriv, hipStream_t s)
-{
-    auto k = k_legendre_synth_batch<SPIN, NCB, F32>;
-    static const int groups = persistent_groups(k, 64);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
-    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64), 0, s, b.d_views, b.d_syn, b.nsyn, ptrs,
-                       b.plans[0]->flush_chunks, deriv, b.d_counter);
-}
-
-template <int SPIN, int NCB, bool F32>
 static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     auto k = k_legendre_anal_batch<SPIN, NCB, F32>;
@@ -1108,25 +1077,6 @@ static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode,
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
     hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * ana_nw(F32, SPIN != 0)), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
                        mode, b.d_counter);
-}
-
-int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s)
-{
-    if (b.nsyn == 0) return SHT_OK;
-    const bool f32 = b.precision == SHT_FP32_MFMA;
-    const int d = deriv ? 1 : 0;
-    const int key = (b.spin ? 4 : 0) + (b.syn_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
-    switch (key) {
-    case 0: launch_synth_batch_t<0, 1, false>(b, ptrs, 0, s); break;
-    case 1: launch_synth_batch_t<0, 1, true>(b, ptrs, 0, s); break;
-    case 2: launch_synth_batch_t<0, 2, false>(b, ptrs, 0, s); break;
-    case 3: launch_synth_batch_t<0, 2, true>(b, ptrs, 0, s); break;
-    case 4: launch_synth_batch_t<2, 1, false>(b, ptrs, d, s); break;
-    case 5: launch_synth_batch_t<2, 1, true>(b, ptrs, d, s); break;
-    case 6: launch_synth_batch_t<2, 2, false>(b, ptrs, d, s); break;
-    default: launch_synth_batch_t<2, 2, true>(b, ptrs, d, s); break;
-    }
-    return check_hip(hipGetLastError(), "batch legendre synthesis launch");
 }
 
 int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)

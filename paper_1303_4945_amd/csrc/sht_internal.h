@@ -53,11 +53,7 @@ struct WaveItem {
     int pad;
 };
 
-// Items of the persistent batch kernels (plan index into the batch's tables).
-struct BatchSynItem {
-    int plan;
-    WaveItem it;
-};
+// Items of the persistent batch analysis kernel (plan index into the batch's tables).
 struct BatchAnaItem {
     int plan;
     int m;
@@ -184,11 +180,10 @@ struct BatchPtrs {
 struct Batch {
     uint32_t magic = kBatchMagic;
     std::vector<Plan *> plans;
-    int spin = 0, precision = 0, syn_ncb = 1, ana_ncb = 1;
+    int spin = 0, precision = 0, ana_ncb = 1;
     bool real_h = false;
-    int nsyn = 0, nana = 0;
+    int nana = 0;
     LegView *d_views = nullptr;
-    BatchSynItem *d_syn = nullptr;
     BatchAnaItem *d_ana = nullptr;
     unsigned *d_counter = nullptr;
     // captured graphs, one per direction, keyed by the user pointers
@@ -206,7 +201,6 @@ int build_synth_items(Plan &p);
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s);
 
 // persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
-int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s);
 int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s);
 int anal_ncb(int spin, int ntrans);
 
