@@ -202,14 +202,31 @@ int sht_ring_fft(sht_plan *p, int direction, const double *in, double *out,
                  void *hip_stream);
 
 /* Algorithmic work of one Legendre step in the given direction after polar
-   skipping: floating-point operations (the recursion counted once per ring
-   slot and degree, the products per transform) and the minimal HBM bytes of
-   a whole transform (inputs, phases written and read once, outputs). */
-int sht_plan_flops(const sht_plan *p, int direction, double *flops, double *hbm_bytes);
+   skipping (the same in both directions, the analysis being the transpose of
+   the synthesis).  With K the kept (m, ring slot, degree) triples (Sect. 3.3),
+   J = ntrans, and per triple r = 4 (spin 0) or 10 (spin s > 0: two chains,
+   Sect. 4.1) flops of recursion and c = 4 or 16 flops of products per
+   transform:
+     flops_fp64  = K r + K J c for SHT_FP64 (recursion on the vector units,
+                   products on FP64 matrix cores), K r for SHT_FP32_MFMA;
+     flops_mfma  = K J c for SHT_FP32_MFMA (FP32 matrix-core products), 0 for
+                   SHT_FP64;
+     hbm_bytes   = the minimal HBM traffic of a whole transform: a_lm and maps
+                   once, the phases written and read once.
+   Any output pointer may be NULL.  SHT_EINVAL for an unknown direction. */
+int sht_plan_flops(const sht_plan *p, int direction, double *flops_fp64, double *flops_mfma,
+                   double *hbm_bytes);
 
-/* Kernel-level statistics of the last sht_execute on this plan: number of
-   Legendre work items and of ring FFT work items (for reports). */
-int sht_plan_info(const sht_plan *p, int64_t *n_legendre_items, int64_t *workspace_bytes);
+/* Size report of a plan: n_legendre_items = wavefront work items of its
+   Legendre synthesis launch (including the padding items of the die-aware
+   order), device_bytes = all device memory the plan owns (tables, work lists,
+   phase workspace, FFT tables).  Either pointer may be NULL. */
+int sht_plan_info(const sht_plan *p, int64_t *n_legendre_items, int64_t *device_bytes);
+
+/* Device buffers currently allocated by the library in this process, and
+   their total size (diagnostics: a failed create call must leave both where
+   they were).  Either pointer may be NULL. */
+int sht_memory_stats(int64_t *live_buffers, int64_t *live_bytes);
 
 /* ---- batches of plans (mixed band limits and grids) ---- */
 

@@ -40,9 +40,14 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(_SO)
+        # SHT_ORACLE_SO: an alternative build of the same source (the sanitizer
+        # test loads an AddressSanitizer build this way)
+        so = os.environ.get("SHT_ORACLE_SO")
+        if not so:
+            so = _SO
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build()
+        lib = ctypes.CDLL(so)
         lib.oracle_lambda.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_double, _dp]
         lib.oracle_lambda.restype = ctypes.c_int

@@ -83,8 +83,9 @@ _sig("sht_plan_destroy", None, _vp)
 _sig("sht_execute", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
 _sig("sht_legendre", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
 _sig("sht_ring_fft", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
-_sig("sht_plan_flops", ctypes.c_int, _vp, ctypes.c_int, _dp, _dp)
+_sig("sht_plan_flops", ctypes.c_int, _vp, ctypes.c_int, _dp, _dp, _dp)
 _sig("sht_plan_info", ctypes.c_int, _vp, _i64p, _i64p)
+_sig("sht_memory_stats", ctypes.c_int, _i64p, _i64p)
 _sig("sht_batch_create", ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp))
 _sig("sht_batch_execute", ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp)
 _sig("sht_batch_destroy", None, _vp)
@@ -100,6 +101,13 @@ def last_error() -> str:
 def _check(rc: int):
     if rc != SHT_OK:
         raise ShtError(rc, last_error())
+
+
+def memory_stats():
+    """(live device buffers, their bytes) allocated by the library."""
+    n, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.sht_memory_stats(ctypes.byref(n), ctypes.byref(b)))
+    return n.value, b.value
 
 
 def nalm(lmax: int, mmax: int) -> int:
@@ -302,14 +310,16 @@ class Plan:
         return self._run(_lib.sht_ring_fft, d, maps, self.phase_shape, stream, out)
 
     def flops(self, direction=ALM2MAP):
-        f, b = ctypes.c_double(), ctypes.c_double()
-        _check(_lib.sht_plan_flops(self._h, direction, ctypes.byref(f), ctypes.byref(b)))
-        return f.value, b.value
+        """(FP64 flops, FP32 matrix-core flops, minimal HBM bytes) of one Legendre
+        step in this direction (see sht_plan_flops)."""
+        f, fm, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.sht_plan_flops(self._h, direction, ctypes.byref(f), ctypes.byref(fm), ctypes.byref(b)))
+        return f.value, fm.value, b.value
 
     def info(self):
         n, w = ctypes.c_int64(), ctypes.c_int64()
         _check(_lib.sht_plan_info(self._h, ctypes.byref(n), ctypes.byref(w)))
-        return dict(legendre_items=n.value, workspace_bytes=w.value)
+        return dict(legendre_items=n.value, device_bytes=w.value)
 
     def autotune(self, budget_seconds: float = 0.1):
         _check(_lib.sht_autotune(self._h, budget_seconds))

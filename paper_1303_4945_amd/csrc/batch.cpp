@@ -167,8 +167,8 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
     if (!b) { set_error("host allocation failed"); return SHT_ENOMEM; }
     int maxj = 0;
     for (int i = 0; i < nplans; ++i) {
-        Plan *p = reinterpret_cast<Plan *>(plans[i]);
-        if (!p || p->magic != kPlanMagic) {
+        Plan *p = plan_of(plans[i]);
+        if (!p) {
             delete b;
             set_error("plan %d is not a valid plan", i);
             return SHT_ESTATE;
@@ -190,8 +190,12 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
         b->real_h = p->real_h;
         maxj = std::max(maxj, p->ntrans);
         b->plans.push_back(p);
+        b->plan_serial.push_back(p->serial);
     }
+    b->device = b->plans[0]->device;
     b->ana_ncb = anal_ncb(b->spin, maxj);
+    b->ana_groups = anal_batch_groups(b->spin, b->ana_ncb, b->precision == SHT_FP32_MFMA, b->device);
+    fault_arm();
     std::vector<BatchAnaItem> aq;
     anal_queue(*b, aq);
     std::vector<LegView> views;
@@ -211,6 +215,7 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
         delete b;
         return rc;
     }
+    reg_add(b, H_BATCH);
     *out = reinterpret_cast<sht_batch *>(b);
     return SHT_OK;
 }
@@ -218,12 +223,14 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
 int sht_batch_execute(sht_batch *h, int direction, const double *const *in, double *const *out,
                       void *hip_stream)
 {
+    if (!reg_live(h, H_BATCH)) { set_error("invalid batch handle"); return SHT_ESTATE; }
     Batch *b = reinterpret_cast<Batch *>(h);
-    if (!b || b->magic != kBatchMagic) { set_error("invalid batch handle"); return SHT_ESTATE; }
     if (!in || !out) { set_error("in and out arrays are required"); return SHT_EINVAL; }
+    if (direction < 0 || direction >= NUM_DIRECTIONS) { set_error("unknown direction %d", direction); return SHT_EINVAL; }
     const int np = (int)b->plans.size();
     for (int i = 0; i < np; ++i) {
-        if (b->plans[i]->magic != kPlanMagic) {
+        uint64_t serial = 0;
+        if (!reg_live(b->plans[i], H_PLAN, &serial) || serial != b->plan_serial[i]) {
             set_error("plan %d of the batch was destroyed", i);
             return SHT_ESTATE;
         }
@@ -236,10 +243,11 @@ int sht_batch_execute(sht_batch *h, int direction, const double *const *in, doub
         if (rc) return rc;
         return finish_launch("sht_batch_execute");
     }
-    std::vector<const void *> key;
+    std::vector<uintptr_t> key;
     for (int i = 0; i < np; ++i) {
-        key.push_back(in[i]);
-        key.push_back(out[i]);
+        key.push_back((uintptr_t)in[i]);
+        key.push_back((uintptr_t)out[i]);
+        key.push_back((uintptr_t)b->plans[i]->generation);
     }
     if (!b->graph[direction] || b->graph_key[direction] != key || b->graph_stream[direction] != s) {
         if (b->graph[direction]) {
@@ -269,18 +277,18 @@ int sht_batch_execute(sht_batch *h, int direction, const double *const *in, doub
 
 void sht_batch_destroy(sht_batch *h)
 {
+    if (!reg_live(h, H_BATCH)) return;
     Batch *b = reinterpret_cast<Batch *>(h);
-    if (!b || b->magic != kBatchMagic) return;
+    reg_remove(b);
     (void)hipDeviceSynchronize();
     batch_free(b);
-    b->magic = kDeadMagic;
     delete b;
 }
 
 int sht_autotune(sht_plan *h, double budget_seconds)
 {
-    Plan *p = reinterpret_cast<Plan *>(h);
-    if (!p || p->magic != kPlanMagic) { set_error("invalid plan handle"); return SHT_ESTATE; }
+    Plan *p = plan_of(h);
+    if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     if (!(budget_seconds >= 0.0)) { set_error("budget must be >= 0"); return SHT_EINVAL; }
     const std::string key = tune_key(*p);
     std::vector<int> cand = {1};

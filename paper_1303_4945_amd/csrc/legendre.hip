@@ -1054,13 +1054,13 @@ int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mo
 
 // ---------------------------------------------------------------- batches
 
-// work groups of a persistent launch: every CU filled to the kernel's occupancy
+// work groups of a persistent launch on a device: every CU filled to the
+// kernel's occupancy
 template <typename K>
-static int persistent_groups(K kernel, int threads)
+static int persistent_groups(K kernel, int threads, int dev)
 {
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    int ncu = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, threads, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 1024;
@@ -1070,13 +1070,33 @@ static int persistent_groups(K kernel, int threads)
 }
 
 template <int SPIN, int NCB, bool F32>
+static int anal_batch_groups_t(int dev)
+{
+    return persistent_groups(k_legendre_anal_batch<SPIN, NCB, F32>, 64 * ana_nw(F32, SPIN != 0), dev);
+}
+
+int anal_batch_groups(int spin, int ncb, bool f32, int dev)
+{
+    const int key = (spin ? 4 : 0) + (ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
+    switch (key) {
+    case 0: return anal_batch_groups_t<0, 1, false>(dev);
+    case 1: return anal_batch_groups_t<0, 1, true>(dev);
+    case 2: return anal_batch_groups_t<0, 2, false>(dev);
+    case 3: return anal_batch_groups_t<0, 2, true>(dev);
+    case 4: return anal_batch_groups_t<2, 1, false>(dev);
+    case 5: return anal_batch_groups_t<2, 1, true>(dev);
+    case 6: return anal_batch_groups_t<2, 2, false>(dev);
+    default: return anal_batch_groups_t<2, 2, true>(dev);
+    }
+}
+
+template <int SPIN, int NCB, bool F32>
 static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     auto k = k_legendre_anal_batch<SPIN, NCB, F32>;
-    static const int groups = persistent_groups(k, 64 * ana_nw(F32, SPIN != 0));
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
-    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(64 * ana_nw(F32, SPIN != 0)), 0, s, b.d_views, b.d_ana, b.nana, ptrs,
-                       mode, b.d_counter);
+    hipLaunchKernelGGL(k, dim3((unsigned)b.ana_groups), dim3(64 * ana_nw(F32, SPIN != 0)), 0, s, b.d_views, b.d_ana,
+                       b.nana, ptrs, mode, b.d_counter);
 }
 
 int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)

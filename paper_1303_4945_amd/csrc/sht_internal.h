@@ -8,34 +8,11 @@
 #include <vector>
 
 #include "../../include/sht.h"
+#include "host.h"
 
 namespace sht {
 
-constexpr uint32_t kGeomMagic = 0x53474d31u;   // live geometry
-constexpr uint32_t kPlanMagic = 0x53504c31u;   // live plan
-constexpr uint32_t kBatchMagic = 0x53424331u;  // live batch
-constexpr uint32_t kDeadMagic = 0xdeadbeefu;
-
-void set_error(const char *fmt, ...);
-
-struct Geom {
-    uint32_t magic = kGeomMagic;
-    int nrings = 0;
-    std::vector<double> theta, phi0, weight;
-    std::vector<int64_t> nphi, ofs;
-    int64_t stride = 1;
-    bool has_weight = false;
-    int64_t npix = 0;
-};
-
-// One recurrence chain slot: a ring and (optionally) its mirror ring.
-// The recursion runs at the representative colatitude t <= pi/2 of the slot;
-// the ring at pi - t (if any) follows from the parity relation.
-struct SlotHost {
-    int yn = -1, ys = -1;       // ring at t and ring at pi - t (-1: none)
-    double cth = 0, sth = 0;    // cos t >= 0, sin t
-    double chalf = 0, shalf = 0;  // cos t/2, sin t/2
-};
+const Geom *geom_of(const sht_geom *g);   // registered geometry or nullptr
 
 // wavefronts per analysis work group: eight for spin > 0 in FP64 (half the
 // passes over a_lm of four; the LDS then holds one work group per CU), four
@@ -58,15 +35,6 @@ struct BatchAnaItem {
     int plan;
     int m;
     int t0;
-    int pad;
-};
-
-// Per-(m, chain) start value: lambda_{l0} = sign * K * cos(t/2)^p * sin(t/2)^q.
-struct StartCoef {
-    double kmant;   // mantissa of K in [0.5, 1)
-    int kexp;       // binary exponent of K
-    int p, q;       // powers of cos(theta/2), sin(theta/2)
-    int sign;       // +1 / -1
     int pad;
 };
 
@@ -103,7 +71,8 @@ struct FftPlan {
 };
 
 struct Plan {
-    uint32_t magic = kPlanMagic;
+    uint64_t serial = 0;             // registry serial of this plan
+    uint64_t generation = 0;         // bumped whenever its work lists change (autotuner)
     int device = 0;
     int lmax = 0, mmax = 0, spin = 0, ntrans = 0, precision = 0, ncomp = 1;
     Geom geom;
@@ -138,30 +107,18 @@ struct Plan {
     double *d_phase = nullptr;       // F / G workspace
     int64_t phase_elems = 0;         // complex elements
     FftPlan fft;
-    double flops_synth = 0, flops_anal = 0, hbm_bytes = 0;
+    double flops_rec = 0, flops_prod = 0, hbm_bytes = 0;   // recursion, products (one direction)
     int64_t n_items = 0;
-    // tuning
-    int synth_waves = 1;
+    PlanShape shape() const
+    {
+        PlanShape ps;
+        ps.lmax = lmax; ps.mmax = mmax; ps.spin = spin; ps.ntrans = ntrans; ps.polar_T = polar_T;
+        return ps;
+    }
 };
 
 constexpr int MAX_BATCH_PLANS = 64;
 
-// Legendre-step operands of the plans of a batch, passed by value to the
-// persistent kernels (so that a captured graph holds them as parameters).
-// directions of sht_execute (SHT_ALM2MAP .. SHT_ALM2MAP_DERIV1_GRAD); the
-// ones that go from a_lm to maps run the synthesis kernels
-constexpr int NUM_DIRECTIONS = 8;
-inline bool synth_direction(int d)
-{
-    return d == SHT_ALM2MAP || d == SHT_MAP2ALM_ADJOINT || d == SHT_ALM2MAP_DERIV1;
-}
-// first-derivative synthesis and its adjoints: spin-1 plans, one a_lm component
-inline bool deriv_direction(int d)
-{
-    return d == SHT_ALM2MAP_DERIV1 || d == SHT_ALM2MAP_DERIV1_ADJOINT || d == SHT_ALM2MAP_DERIV1_GRAD;
-}
-// ring weights in the FFT step: analysis and the adjoint of analysis
-inline bool weighted_direction(int d) { return d == SHT_MAP2ALM || d == SHT_MAP2ALM_ADJOINT; }
 // analysis kernel mode bits
 constexpr int ANA_MODE_GRAD = 1;    // real-field gradient factor fac_m
 constexpr int ANA_MODE_DERIV = 2;   // adjoint of the derivative synthesis
@@ -172,23 +129,28 @@ inline int anal_mode(int d, bool real_h)
            (deriv_direction(d) ? ANA_MODE_DERIV : 0);
 }
 
+// Legendre-step operands of the plans of a batch, passed by value to the
+// persistent kernels (so that a captured graph holds them as parameters).
 struct BatchPtrs {
     const double *in[MAX_BATCH_PLANS];
     double *out[MAX_BATCH_PLANS];
 };
 
 struct Batch {
-    uint32_t magic = kBatchMagic;
     std::vector<Plan *> plans;
+    std::vector<uint64_t> plan_serial;   // registry serials of the borrowed plans
+    int device = 0;
+    int ana_groups = 1;                  // work groups of the persistent analysis launch
     int spin = 0, precision = 0, ana_ncb = 1;
     bool real_h = false;
     int nana = 0;
     LegView *d_views = nullptr;
     BatchAnaItem *d_ana = nullptr;
     unsigned *d_counter = nullptr;
-    // captured graphs, one per direction, keyed by the user pointers
+    // captured graphs, one per direction, keyed by the user pointers and the
+    // plans' generations (a retuned plan has new item lists and launch shapes)
     hipGraphExec_t graph[NUM_DIRECTIONS] = {};
-    std::vector<const void *> graph_key[NUM_DIRECTIONS];
+    std::vector<uintptr_t> graph_key[NUM_DIRECTIONS];
     hipStream_t graph_stream[NUM_DIRECTIONS] = {};
 };
 
@@ -202,6 +164,8 @@ int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mo
 
 // persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
 int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s);
+// work groups of the persistent analysis launch on the given device
+int anal_batch_groups(int spin, int ncb, bool f32, int device);
 int anal_ncb(int spin, int ntrans);
 
 // ring FFT (ringfft.hip)
@@ -222,6 +186,7 @@ int dev_upload(void *dst, const void *src, size_t bytes, const char *what);
 int check_hip(hipError_t e, const char *what);
 int check_exec_args(const Plan *p, int direction, const void *in, const void *out, bool fft_only,
                     bool leg_only);
+Plan *plan_of(sht_plan *h);   // registered plan or nullptr
 int finish_launch(const char *what);
 
 }  // namespace sht

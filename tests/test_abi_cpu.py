@@ -130,3 +130,32 @@ def test_plan_opts_layout_matches_header(tmp_path):
     out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert out[0] == ctypes.sizeof(sht.PlanOpts)
     assert out[1:] == [getattr(sht.PlanOpts, f).offset for f in fields]
+
+
+def test_destroyed_and_foreign_handles_are_rejected():
+    """Handles are looked up in the library's registry before they are read:
+    a destroyed geometry, a pointer that never was a handle and a handle of
+    the wrong kind all give SHT_ESTATE (and no read of freed memory)."""
+    import ctypes
+    sht = _sht()
+    h = ctypes.c_void_p()
+    assert sht.lib.sht_geom_gauss(8, 17, 0.0, ctypes.byref(h)) == sht.SHT_OK
+    n = ctypes.c_int()
+    assert sht.lib.sht_geom_info(h, ctypes.byref(n), None) == sht.SHT_OK and n.value == 8
+    sht.lib.sht_geom_destroy(h)
+    assert sht.lib.sht_geom_info(h, ctypes.byref(n), None) == sht.SHT_ESTATE
+    sht.lib.sht_geom_destroy(h)   # a second destroy is a no-op
+    junk = (ctypes.c_double * 16)()
+    assert sht.lib.sht_geom_info(ctypes.cast(junk, ctypes.c_void_p), None, None) == sht.SHT_ESTATE
+    g = sht.Geometry.gauss(4, 9)
+    # a geometry handle passed where a plan is expected
+    assert sht.lib.sht_execute(g._h, 0, None, None, None) == sht.SHT_ESTATE
+    f = ctypes.c_double()
+    assert sht.lib.sht_plan_flops(g._h, 0, ctypes.byref(f), None, None) == sht.SHT_ESTATE
+    assert sht.lib.sht_batch_execute(g._h, 0, None, None, None) == sht.SHT_ESTATE
+
+
+def test_memory_stats_without_device():
+    sht = _sht()
+    n, b = sht.memory_stats()
+    assert n >= 0 and b >= 0

@@ -105,6 +105,72 @@ def test_lambda_s0_high_precision(lmax, m, theta):
     assert err < 1e-13, err
 
 
+def _mp_lambda_spin2(lmax, m, theta, dps=50):
+    """+-2 lambda from the scalar harmonics in 50-digit arithmetic, by applying
+    the spin-raising operator twice to Y_lm (a route that shares nothing with
+    Eq. 11): with Y = lambda_l (scalar, from _mp_lambda_s0), x = cos, s = sin,
+      s dY/dtheta = l x Y - sqrt((2l+1)/(2l-1)) sqrt(l^2 - m^2) lambda_{l-1},
+      base  = -l(l+1) Y - 2 (x/s) dY/dtheta + 2 m^2/s^2 Y,
+      cross = (2m/s) (dY/dtheta - (x/s) Y),
+      +-2 lambda = (base -+ cross) / sqrt((l-1) l (l+1) (l+2)).
+    Returns {l: (lambda_{+2}, lambda_{-2})}."""
+    lam = _mp_lambda_s0(lmax, m, theta, dps)
+    out = {}
+    with mpmath.workdps(dps):
+        th = mpmath.mpf(theta)
+        x, s = mpmath.cos(th), mpmath.sin(th)
+        for l in range(max(m, 2), lmax + 1):
+            y = lam[l]
+            yp = lam[l - 1] if l - 1 >= m else mpmath.mpf(0)
+            dy = (l * x * y - mpmath.sqrt(mpmath.mpf(2 * l + 1) / (2 * l - 1))
+                  * mpmath.sqrt(mpmath.mpf(l * l - m * m)) * yp) / s
+            base = -l * (l + 1) * y - 2 * x / s * dy + 2 * m * m / (s * s) * y
+            cross = 2 * m / s * (dy - x / s * y)
+            norm = 1 / mpmath.sqrt(mpmath.mpf((l - 1) * l * (l + 1) * (l + 2)))
+            out[l] = (norm * (base - cross), norm * (base + cross))
+    return out
+
+
+def test_spin2_from_scalar_matches_explicit_sum():
+    """The spin-raising route of _mp_lambda_spin2 equals Wigner's explicit sum
+    with Eq. 10's normalisation at low degrees (fixes its sign convention)."""
+    for theta in (0.3, 1.1, 2.5):
+        for m in (0, 1, 3, 7):
+            ref = _mp_lambda_spin2(16, m, theta)
+            for l in range(max(m, 2), 17):
+                for k, s in enumerate((2, -2)):
+                    d = _mp_d_explicit(l, -m, s, theta)
+                    direct = (-1) ** m * math.sqrt((2 * l + 1) / FOURPI) * d
+                    assert abs(float(ref[l][k]) - direct) < 1e-13, (theta, m, l, s)
+
+
+@pytest.mark.parametrize("theta", [5.9e-4, 0.05, 1.3])
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 2000, 4095])
+def test_lambda_s2_high_precision(theta, m):
+    """The oracle's spin +-2 recursion (Eq. 11, extended exponent) up to
+    l = 4095 against the 50-digit spin-raising route from the scalar
+    harmonics; columns that lie entirely below the double range must come out
+    as exact zeros.  Tolerance: 1e-13 normwise, except at the polar-most
+    colatitude, where Eq. 11 sees theta only through x = cos theta, which
+    holds theta to an absolute precision of about u / theta (u = 2^-64, the
+    long double unit): at theta = 5.9e-4 that is 9e-17, and the phase of a
+    degree-4095 column moves by l times that, 4e-13."""
+    lmax = 4095
+    tol = 5e-13 if theta < 0.01 else 1e-13
+    ref = _mp_lambda_spin2(lmax, m, theta)
+    ls = sorted(ref)
+    for k, s in enumerate((2, -2)):
+        lam = oracle.lam(lmax, m, s, theta)
+        refv = np.array([float(ref[l][k]) for l in ls])
+        got = lam[ls]
+        scale = np.max(np.abs(refv))
+        if scale == 0.0:
+            assert np.all(got == 0.0), (s, m, theta)
+            continue
+        err = np.max(np.abs(got - refv)) / scale
+        assert err < tol, (s, err)
+
+
 def test_lambda_s0_legenp_sample():
     """mpmath's associated Legendre function at one mid-latitude sample."""
     l, m, theta = 1200, 500, 0.8
