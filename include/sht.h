@@ -231,19 +231,66 @@ int sht_memory_stats(int64_t *live_buffers, int64_t *live_bytes);
 /* ---- batches of plans (mixed band limits and grids) ---- */
 
 /* A batch runs several plans (same spin, precision and coefficient storage;
-   one direction per call) as one stream-ordered unit: the Legendre analyses of
-   every plan are merged into one cost-ordered persistent launch, the Legendre
-   syntheses and the ring FFTs run plan by plan, and on a non-null stream the
-   whole sequence is captured once into a HIP graph and replayed.  The plans
-   are borrowed and must outlive the batch. */
+   one direction per call) as one stream-ordered unit (Sect. 3.2's simultaneous
+   transforms, with mixed band limits and grids): the Legendre analyses of
+   every plan are merged into one persistent launch over a queue of items
+   popped by an atomic counter; the Legendre syntheses (each plan's die-aware
+   item list) and the ring FFTs run per plan, on concurrent streams; on a
+   non-null stream the whole sequence is captured once into a HIP graph and
+   replayed (captured again when the buffers, the stream or the tuning of a
+   plan change).  The plans are borrowed and must outlive the batch; results
+   equal the plans' own bit for bit. */
 int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out);
 int sht_batch_execute(sht_batch *b, int direction, const double *const *in,
                       double *const *out, void *hip_stream);
 void sht_batch_destroy(sht_batch *b);
 
-/* Pick tile parameters for a plan by timing candidates on scratch data for
-   about budget_seconds (Sect. 3.2); results are cached in the file named by
-   $SHT_TUNE_CACHE (if set). */
+/* Legendre step only of every plan of the batch (as sht_legendre per plan):
+   in/out hold one phase buffer and one coefficient buffer per plan.  Plain
+   launches on hip_stream (no graph); the analysis directions run the batch's
+   persistent launch. */
+int sht_batch_legendre(sht_batch *b, int direction, const double *const *in,
+                       double *const *out, void *hip_stream);
+
+/* Scheduling of a batch:
+   queue_order  SHT_QUEUE_COST: analysis items (plan, m, transform group)
+                ordered by decreasing cost (degree range x active slot tiles);
+                SHT_QUEUE_MPAIRS: items are pairs (m, mmax - m) of one plan,
+                whose cost is nearly the same for every pair (Sect. 4.2's
+                load balance), ordered by decreasing pair cost;
+   concurrent   1: every plan's launch chain (synthesis: Legendre step then
+                ring FFTs; analysis: ring FFTs) runs on a stream of its own
+                between a fork and a join on the caller's stream, so that small
+                plans fill the gaps of large ones; 0: one stream.
+   Defaults: SHT_QUEUE_COST, concurrent 1.  Results do not depend on either. */
+enum { SHT_QUEUE_COST = 0, SHT_QUEUE_MPAIRS = 1 };
+int sht_batch_configure(sht_batch *b, int queue_order, int concurrent);
+
+/* Launch-shape parameters of a plan's Legendre kernels (Sect. 3.2: block sizes
+   are machine dependent and picked by measurement).  Every combination gives
+   the same results bit for bit; only the speed differs. */
+typedef struct sht_tuning {
+    int synth_ncb;      /* synthesis: 16-column blocks per wavefront (1 or 2) */
+    int synth_mblock;   /* synthesis: consecutive m values dealt to one
+                           accelerator die (1 .. 64) */
+    int anal_ncb;       /* analysis: 16-column blocks per work group (1 or 2) */
+    int anal_tpw;       /* analysis: slot tiles per wavefront and pass (1 or 2) */
+    int reserved[12];
+} sht_tuning;
+
+/* Current tuning of a plan. */
+int sht_plan_get_tuning(const sht_plan *p, sht_tuning *t);
+/* Set a tuning (SHT_EUNSUPPORTED for a combination that is not built for the
+   plan's spin and precision; the plan keeps its previous tuning then).  Not
+   while work of the plan is in flight. */
+int sht_plan_set_tuning(sht_plan *p, const sht_tuning *t);
+
+/* Pick the tuning of a plan by timing the candidate combinations on scratch
+   data (one Legendre synthesis and analysis each) for about budget_seconds;
+   results are cached in the text file named by $SHT_TUNE_CACHE (if set), one
+   line per plan shape, so that a later plan of the same shape takes the cached
+   choice without timing (budget 0: only the cache is consulted).  Batches that
+   hold the plan capture their launches again at their next execution. */
 int sht_autotune(sht_plan *p, double budget_seconds);
 
 const char *sht_last_error(void);

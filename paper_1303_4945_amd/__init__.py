@@ -89,7 +89,18 @@ _sig("sht_memory_stats", ctypes.c_int, _i64p, _i64p)
 _sig("sht_batch_create", ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp))
 _sig("sht_batch_execute", ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp)
 _sig("sht_batch_destroy", None, _vp)
+_sig("sht_batch_legendre", ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp)
+_sig("sht_batch_configure", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int)
 _sig("sht_autotune", ctypes.c_int, _vp, ctypes.c_double)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("synth_ncb", ctypes.c_int), ("synth_mblock", ctypes.c_int), ("anal_ncb", ctypes.c_int),
+                ("anal_tpw", ctypes.c_int), ("reserved", ctypes.c_int * 12)]
+
+
+_sig("sht_plan_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(Tuning))
+_sig("sht_plan_set_tuning", ctypes.c_int, _vp, ctypes.POINTER(Tuning))
 
 lib = _lib
 
@@ -324,6 +335,22 @@ class Plan:
     def autotune(self, budget_seconds: float = 0.1):
         _check(_lib.sht_autotune(self._h, budget_seconds))
 
+    _TUNING_KEYS = ("synth_ncb", "synth_mblock", "anal_ncb", "anal_tpw")
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(_lib.sht_plan_get_tuning(self._h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k in self._TUNING_KEYS}
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        _check(_lib.sht_plan_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in kw.items():
+            if k not in self._TUNING_KEYS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(_lib.sht_plan_set_tuning(self._h, ctypes.byref(t)))
+
     def __del__(self):
         h, fn = getattr(self, "_h", None), getattr(self, "_destroy", None)
         if h and fn is not None:
@@ -331,11 +358,17 @@ class Plan:
             self._h = None
 
 
+QUEUE_COST, QUEUE_MPAIRS = 0, 1
+
+
 class Batch:
-    """Several plans (same spin and precision) executed as one unit: one
-    persistent Legendre launch over all plans plus every plan's ring FFTs; on a
-    non-default stream the launches are captured once into a HIP graph per
-    direction (re-captured when the buffers change) and replayed."""
+    """Several plans (same spin and precision) executed as one unit: the
+    Legendre analyses of all plans in one persistent launch over a shared
+    queue; each plan's Legendre synthesis (its die-aware item list) and ring
+    FFTs on a stream of its own between a fork and a join; on a non-default
+    stream the launches are captured once into a HIP graph per direction
+    (captured again when the buffers, the stream or a plan's tuning change)
+    and replayed."""
 
     def __init__(self, plans):
         self.plans = list(plans)
@@ -360,6 +393,17 @@ class Batch:
         a_in = (_vp * n)(*[x.data_ptr() for x in ins])
         a_out = (_vp * n)(*[y.data_ptr() for y in outs])
         _check(_lib.sht_batch_execute(self._h, direction, a_in, a_out, _stream_handle(stream)))
+        return outs
+
+    def configure(self, queue_order: int = QUEUE_COST, concurrent: bool = True):
+        _check(_lib.sht_batch_configure(self._h, int(queue_order), 1 if concurrent else 0))
+
+    def legendre(self, direction, ins, outs, stream=None):
+        """Legendre step only of every plan (phases <-> coefficients)."""
+        n = len(self.plans)
+        a_in = (_vp * n)(*[x.data_ptr() for x in ins])
+        a_out = (_vp * n)(*[y.data_ptr() for y in outs])
+        _check(_lib.sht_batch_legendre(self._h, direction, a_in, a_out, _stream_handle(stream)))
         return outs
 
     def alm2map(self, alms, outs=None, stream=None):

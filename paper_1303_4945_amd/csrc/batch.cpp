@@ -22,25 +22,44 @@ void batch_free(Batch *b)
 {
     for (int d = 0; d < NUM_DIRECTIONS; ++d)
         if (b->graph[d]) (void)hipGraphExecDestroy(b->graph[d]);
+    for (hipStream_t s : b->aux) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    b->aux.clear();
+    b->join.clear();
     dev_free(b->d_views);
     dev_free(b->d_ana);
     dev_free(b->d_counter);
 }
 
-// Queue of analysis items (m, transform group) of all plans, by cost.
+// Queue of analysis items of all plans.  SHT_QUEUE_COST: items (plan, m,
+// transform group) by decreasing cost (degree range x passes over the active
+// slot tiles); SHT_QUEUE_MPAIRS: items (plan, m and mmax - m, group), whose
+// degree ranges add up to about lmax + 2, by decreasing pair cost.
 void anal_queue(const Batch &b, std::vector<BatchAnaItem> &q)
 {
     const int cpj = b.spin ? 4 : 2;
     const int jpg = b.ana_ncb * 16 / cpj;
+    const int nw = ana_nw(b.precision == SHT_FP32_MFMA, b.spin != 0);
     std::vector<std::pair<double, BatchAnaItem>> v;
     for (int pi = 0; pi < (int)b.plans.size(); ++pi) {
         const Plan &p = *b.plans[pi];
-        for (int m = 0; m <= p.mmax; ++m) {
+        auto cost = [&](int m) {
             int act = 0;
             for (int t = 0; t < p.ntiles; ++t) act += p.tile_mlim[t] >= m;
-            const int nw = ana_nw(b.precision == SHT_FP32_MFMA, b.spin != 0);
-            const double cost = (double)(p.lmax + 1 - std::max(m, p.spin)) * (double)((act + nw - 1) / nw + 1);
-            for (int t0 = 0; t0 < p.ntrans; t0 += jpg) v.push_back({cost, BatchAnaItem{pi, m, t0, 0}});
+            return (double)(p.lmax + 1 - std::max(m, p.spin)) * (double)((act + nw - 1) / nw + 1);
+        };
+        if (b.queue_order == SHT_QUEUE_MPAIRS) {
+            for (int m = 0; m <= p.mmax - m; ++m) {
+                const int m2 = p.mmax - m;
+                const double c = cost(m) + (m2 != m ? cost(m2) : 0.0);
+                for (int t0 = 0; t0 < p.ntrans; t0 += jpg)
+                    v.push_back({c, BatchAnaItem{pi, m, t0, m2 != m ? m2 : -1}});
+            }
+        } else {
+            for (int m = 0; m <= p.mmax; ++m) {
+                const double c = cost(m);
+                for (int t0 = 0; t0 < p.ntrans; t0 += jpg) v.push_back({c, BatchAnaItem{pi, m, t0, -1}});
+            }
         }
     }
     std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
@@ -48,52 +67,124 @@ void anal_queue(const Batch &b, std::vector<BatchAnaItem> &q)
     for (auto &e : v) q.push_back(e.second);
 }
 
-// Everything one execution of the batch puts on the stream.
-int batch_enqueue(Batch &b, int direction, const double *const *in, double *const *out, hipStream_t s)
+int upload_queue(Batch &b)
+{
+    std::vector<BatchAnaItem> aq;
+    anal_queue(b, aq);
+    b.nana = (int)aq.size();
+    dev_free(b.d_ana);
+    b.d_ana = nullptr;
+    int rc;
+    if ((rc = dev_alloc((void **)&b.d_ana, std::max<size_t>(1, aq.size()) * sizeof(BatchAnaItem), "batch tables")))
+        return rc;
+    if (!aq.empty()) return dev_upload(b.d_ana, aq.data(), aq.size() * sizeof(BatchAnaItem), "batch tables");
+    return SHT_OK;
+}
+
+// Stream of plan i's launch chain: its own stream when the batch runs plans
+// concurrently (forked from and joined into the caller's stream), else the
+// caller's stream.
+hipStream_t chain_stream(const Batch &b, int i, hipStream_t s) { return b.concurrent ? b.aux[i] : s; }
+
+int fork_chains(Batch &b, hipStream_t s)
+{
+    if (!b.concurrent) return SHT_OK;
+    hipEvent_t fork = b.join.back();
+    int rc = check_hip(hipEventRecord(fork, s), "batch fork");
+    for (size_t i = 0; i < b.plans.size() && !rc; ++i)
+        rc = check_hip(hipStreamWaitEvent(b.aux[i], fork, 0), "batch fork");
+    return rc;
+}
+
+int join_chains(Batch &b, hipStream_t s)
+{
+    if (!b.concurrent) return SHT_OK;
+    int rc = SHT_OK;
+    for (size_t i = 0; i < b.plans.size() && !rc; ++i) {
+        rc = check_hip(hipEventRecord(b.join[i], b.aux[i]), "batch join");
+        if (!rc) rc = check_hip(hipStreamWaitEvent(s, b.join[i], 0), "batch join");
+    }
+    return rc;
+}
+
+// Legendre synthesis of plan i into phase (with the real-harmonics conversion first).
+int plan_legendre_synth(Batch &b, int i, int direction, const double *in, double *phase, hipStream_t s)
+{
+    Plan &p = *b.plans[i];
+    const double *a = in;
+    int rc;
+    if (b.real_h) {
+        if ((rc = launch_real_harm(p, in, p.d_rh, deriv_direction(direction) ? 1 : p.ncomp, true, s))) return rc;
+        a = p.d_rh;
+    }
+    return launch_legendre_synth(p, a, phase, deriv_direction(direction), s);
+}
+
+// Persistent Legendre analysis over all plans, then the real-harmonics conversion.
+int batch_legendre_anal(Batch &b, int direction, const double *const *phase, double *const *out, hipStream_t s)
 {
     BatchPtrs ptrs;
     std::memset(&ptrs, 0, sizeof(ptrs));
     const int np = (int)b.plans.size();
+    for (int i = 0; i < np; ++i) {
+        ptrs.in[i] = phase[i];
+        ptrs.out[i] = out[i];
+    }
     int rc;
+    if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction, b.real_h), s))) return rc;
+    if (b.real_h)
+        for (int i = 0; i < np; ++i)
+            if ((rc = launch_real_harm(*b.plans[i], out[i], out[i], deriv_direction(direction) ? 1 : b.plans[i]->ncomp,
+                                       false, s)))
+                return rc;
+    return SHT_OK;
+}
+
+// Everything one execution of the batch puts on the stream.
+int batch_enqueue(Batch &b, int direction, const double *const *in, double *const *out, hipStream_t s)
+{
+    const int np = (int)b.plans.size();
+    int rc;
+    if ((rc = fork_chains(b, s))) return rc;
     if (synth_direction(direction)) {
-        // each plan's own die-aware item list (its a_lm rows and phase lines stay
-        // in one L2; one cost-ordered queue over all plans measured slower)
+        // per plan: its die-aware Legendre item list, then its ring FFTs
         for (int i = 0; i < np; ++i) {
-            const double *a = in[i];
-            if (b.real_h) {
-                if ((rc = launch_real_harm(*b.plans[i], in[i], b.plans[i]->d_rh,
-                                           deriv_direction(direction) ? 1 : b.plans[i]->ncomp, true, s)))
-                    return rc;
-                a = b.plans[i]->d_rh;
-            }
-            if ((rc = launch_legendre_synth(*b.plans[i], a, b.plans[i]->d_phase, deriv_direction(direction), s)))
+            const hipStream_t cs = chain_stream(b, i, s);
+            if ((rc = plan_legendre_synth(b, i, direction, in[i], b.plans[i]->d_phase, cs))) return rc;
+            if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i], weighted_direction(direction), cs)))
                 return rc;
         }
-        for (int i = 0; i < np; ++i)
-            if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i],
-                                        weighted_direction(direction), s)))
-                return rc;
-    } else {
-        for (int i = 0; i < np; ++i)
-            if ((rc = launch_ring_anal(*b.plans[i], in[i], b.plans[i]->d_phase, weighted_direction(direction),
-                                       s)))
-                return rc;
-        for (int i = 0; i < np; ++i) {
-            ptrs.in[i] = b.plans[i]->d_phase;
-            ptrs.out[i] = out[i];
+        return join_chains(b, s);
+    }
+    for (int i = 0; i < np; ++i)
+        if ((rc = launch_ring_anal(*b.plans[i], in[i], b.plans[i]->d_phase, weighted_direction(direction),
+                                   chain_stream(b, i, s))))
+            return rc;
+    if ((rc = join_chains(b, s))) return rc;
+    std::vector<const double *> ph(np);
+    for (int i = 0; i < np; ++i) ph[i] = b.plans[i]->d_phase;
+    return batch_legendre_anal(b, direction, ph.data(), out, s);
+}
+
+int check_batch_args(Batch *b, int direction, const double *const *in, double *const *out, bool leg_only)
+{
+    if (!in || !out) { set_error("in and out arrays are required"); return SHT_EINVAL; }
+    if (direction < 0 || direction >= NUM_DIRECTIONS) { set_error("unknown direction %d", direction); return SHT_EINVAL; }
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        uint64_t serial = 0;
+        if (!reg_live(b->plans[i], H_PLAN, &serial) || serial != b->plan_serial[i]) {
+            set_error("plan %zu of the batch was destroyed", i);
+            return SHT_ESTATE;
         }
-        if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction, b.real_h), s))) return rc;
-        if (b.real_h)
-            for (int i = 0; i < np; ++i)
-                if ((rc = launch_real_harm(*b.plans[i], out[i], out[i],
-                                           deriv_direction(direction) ? 1 : b.plans[i]->ncomp, false, s)))
-                    return rc;
+        int rc = check_exec_args(b->plans[i], direction, in[i], out[i], false, leg_only);
+        if (rc) return rc;
     }
     return SHT_OK;
 }
 
-// Time one Legendre synthesis of the plan (ms per launch) on scratch input.
-int time_synth(Plan &p, const double *alm, int reps, double &ms)
+// Mean time (ms) of `reps` launches of fn after one warm-up launch.
+template <typename F>
+int time_launches(F fn, int reps, double &ms)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -101,9 +192,9 @@ int time_synth(Plan &p, const double *alm, int reps, double &ms)
         set_error("event creation failed");
         return SHT_EDEVICE;
     }
-    int rc = launch_legendre_synth(p, alm, p.d_phase, false, nullptr);   // warm-up
+    int rc = fn();   // warm-up
     if (!rc) rc = check_hip(hipEventRecord(e0, nullptr), "autotune");
-    for (int r = 0; r < reps && !rc; ++r) rc = launch_legendre_synth(p, alm, p.d_phase, false, nullptr);
+    for (int r = 0; r < reps && !rc; ++r) rc = fn();
     if (!rc) rc = check_hip(hipEventRecord(e1, nullptr), "autotune");
     if (!rc) rc = check_hip(hipEventSynchronize(e1), "autotune");
     float t = 0.f;
@@ -117,36 +208,59 @@ int time_synth(Plan &p, const double *alm, int reps, double &ms)
 std::string tune_key(const Plan &p)
 {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "synth_ncb gfx950 lmax=%d mmax=%d spin=%d ntrans=%d nrings=%d prec=%d",
+    std::snprintf(buf, sizeof buf, "sht-tuning gfx950 lmax=%d mmax=%d spin=%d ntrans=%d nrings=%d prec=%d",
                   p.lmax, p.mmax, p.spin, p.ntrans, p.geom.nrings, p.precision);
     return buf;
 }
 
-int tune_cache_lookup(const std::string &key)
+std::string tune_text(const sht_tuning &t)
+{
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "synth_ncb=%d,synth_mblock=%d,anal_ncb=%d,anal_tpw=%d", t.synth_ncb,
+                  t.synth_mblock, t.anal_ncb, t.anal_tpw);
+    return buf;
+}
+
+bool tune_parse(const char *s, sht_tuning &t)
+{
+    sht_tuning r{};
+    if (std::sscanf(s, "synth_ncb=%d,synth_mblock=%d,anal_ncb=%d,anal_tpw=%d", &r.synth_ncb, &r.synth_mblock,
+                    &r.anal_ncb, &r.anal_tpw) != 4)
+        return false;
+    t = r;
+    return true;
+}
+
+// the last line of the cache file with this key (false: none)
+bool tune_cache_lookup(const std::string &key, sht_tuning &t)
 {
     const char *path = std::getenv("SHT_TUNE_CACHE");
-    if (!path || !*path) return -1;
+    if (!path || !*path) return false;
     FILE *f = std::fopen(path, "r");
-    if (!f) return -1;
+    if (!f) return false;
     char line[512];
-    int val = -1;
+    bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         std::string l(line);
         const size_t bar = l.rfind('|');
         if (bar == std::string::npos) continue;
-        if (l.substr(0, bar) == key) val = std::atoi(l.c_str() + bar + 1);
+        sht_tuning c{};
+        if (l.substr(0, bar) == key && tune_parse(l.c_str() + bar + 1, c)) {
+            t = c;
+            found = true;
+        }
     }
     std::fclose(f);
-    return val;
+    return found;
 }
 
-void tune_cache_store(const std::string &key, int val)
+void tune_cache_store(const std::string &key, const sht_tuning &t)
 {
     const char *path = std::getenv("SHT_TUNE_CACHE");
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s|%d\n", key.c_str(), val);
+    std::fprintf(f, "%s|%s\n", key.c_str(), tune_text(t).c_str());
     std::fclose(f);
 }
 
@@ -196,21 +310,27 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
     b->ana_ncb = anal_ncb(b->spin, maxj);
     b->ana_groups = anal_batch_groups(b->spin, b->ana_ncb, b->precision == SHT_FP32_MFMA, b->device);
     fault_arm();
-    std::vector<BatchAnaItem> aq;
-    anal_queue(*b, aq);
     std::vector<LegView> views;
     for (Plan *p : b->plans) views.push_back(make_leg_view(*p));
-    b->nana = (int)aq.size();
     int rc;
     if ((rc = dev_alloc((void **)&b->d_views, views.size() * sizeof(LegView), "batch tables")) ||
         (rc = dev_upload(b->d_views, views.data(), views.size() * sizeof(LegView), "batch tables")) ||
-        (rc = dev_alloc((void **)&b->d_ana, std::max<size_t>(1, aq.size()) * sizeof(BatchAnaItem), "batch tables")) ||
-        (rc = dev_alloc((void **)&b->d_counter, 64, "batch counter"))) {
+        (rc = upload_queue(*b)) || (rc = dev_alloc((void **)&b->d_counter, 64, "batch counter"))) {
         batch_free(b);
         delete b;
         return rc;
     }
-    if (!aq.empty() && (rc = dev_upload(b->d_ana, aq.data(), aq.size() * sizeof(BatchAnaItem), "batch tables"))) {
+    for (int i = 0; i <= nplans && !rc; ++i) {
+        hipEvent_t e = nullptr;
+        rc = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "batch events");
+        if (!rc) b->join.push_back(e);
+        if (i < nplans && !rc) {
+            hipStream_t st = nullptr;
+            rc = check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "batch streams");
+            if (!rc) b->aux.push_back(st);
+        }
+    }
+    if (rc) {
         batch_free(b);
         delete b;
         return rc;
@@ -220,23 +340,65 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
     return SHT_OK;
 }
 
+int sht_batch_configure(sht_batch *h, int queue_order, int concurrent)
+{
+    if (!reg_live(h, H_BATCH)) { set_error("invalid batch handle"); return SHT_ESTATE; }
+    Batch *b = reinterpret_cast<Batch *>(h);
+    if (queue_order != SHT_QUEUE_COST && queue_order != SHT_QUEUE_MPAIRS) {
+        set_error("unknown queue order %d", queue_order);
+        return SHT_EINVAL;
+    }
+    if (concurrent != 0 && concurrent != 1) { set_error("concurrent must be 0 or 1"); return SHT_EINVAL; }
+    (void)hipDeviceSynchronize();
+    fault_arm();
+    const int old_order = b->queue_order;
+    b->queue_order = queue_order;
+    b->concurrent = concurrent;
+    int rc = upload_queue(*b);
+    if (rc) {
+        b->queue_order = old_order;
+        (void)upload_queue(*b);
+        return rc;
+    }
+    for (int d = 0; d < NUM_DIRECTIONS; ++d)
+        if (b->graph[d]) {
+            (void)hipGraphExecDestroy(b->graph[d]);
+            b->graph[d] = nullptr;
+        }
+    return SHT_OK;
+}
+
+int sht_batch_legendre(sht_batch *h, int direction, const double *const *in, double *const *out,
+                       void *hip_stream)
+{
+    if (!reg_live(h, H_BATCH)) { set_error("invalid batch handle"); return SHT_ESTATE; }
+    Batch *b = reinterpret_cast<Batch *>(h);
+    int rc = check_batch_args(b, direction, in, out, true);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int np = (int)b->plans.size();
+    if (synth_direction(direction)) {
+        if ((rc = fork_chains(*b, s))) return rc;
+        for (int i = 0; i < np; ++i) {
+            const hipStream_t cs = chain_stream(*b, i, s);
+            if ((rc = plan_legendre_synth(*b, i, direction, in[i], out[i], cs))) return rc;
+            if ((rc = launch_phase_tail_zero(*b->plans[i], out[i], cs))) return rc;
+        }
+        if ((rc = join_chains(*b, s))) return rc;
+    } else {
+        if ((rc = batch_legendre_anal(*b, direction, in, out, s))) return rc;
+    }
+    return finish_launch("sht_batch_legendre");
+}
+
 int sht_batch_execute(sht_batch *h, int direction, const double *const *in, double *const *out,
                       void *hip_stream)
 {
     if (!reg_live(h, H_BATCH)) { set_error("invalid batch handle"); return SHT_ESTATE; }
     Batch *b = reinterpret_cast<Batch *>(h);
-    if (!in || !out) { set_error("in and out arrays are required"); return SHT_EINVAL; }
-    if (direction < 0 || direction >= NUM_DIRECTIONS) { set_error("unknown direction %d", direction); return SHT_EINVAL; }
+    int rc0 = check_batch_args(b, direction, in, out, false);
+    if (rc0) return rc0;
     const int np = (int)b->plans.size();
-    for (int i = 0; i < np; ++i) {
-        uint64_t serial = 0;
-        if (!reg_live(b->plans[i], H_PLAN, &serial) || serial != b->plan_serial[i]) {
-            set_error("plan %d of the batch was destroyed", i);
-            return SHT_ESTATE;
-        }
-        int rc = check_exec_args(b->plans[i], direction, in[i], out[i], false, false);
-        if (rc) return rc;
-    }
     hipStream_t s = (hipStream_t)hip_stream;
     if (!s) {   // the null stream cannot be captured: plain launches
         int rc = batch_enqueue(*b, direction, in, out, s);
@@ -290,46 +452,69 @@ int sht_autotune(sht_plan *h, double budget_seconds)
     Plan *p = plan_of(h);
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     if (!(budget_seconds >= 0.0)) { set_error("budget must be >= 0"); return SHT_EINVAL; }
+    fault_arm();
     const std::string key = tune_key(*p);
-    std::vector<int> cand = {1};
-    if (p->ntrans * (p->spin ? 4 : 2) > 16) cand.push_back(2);
-    const int cached = tune_cache_lookup(key);
-    if (cached > 0 && std::find(cand.begin(), cand.end(), cached) != cand.end()) {
-        if (cached != p->synth_ncb) {
-            p->synth_ncb = cached;
-            return build_synth_items(*p);
-        }
-        return SHT_OK;
+    sht_tuning cached{};
+    if (tune_cache_lookup(key, cached) && tuning_check(*p, cached) == SHT_OK) return apply_tuning(*p, cached);
+    if (budget_seconds == 0.0) return SHT_OK;
+
+    // candidates of each knob; the synthesis and the analysis knobs are
+    // independent of each other and are timed on their own kernels
+    const int cols = p->ntrans * (p->spin ? 4 : 2);
+    std::vector<int> s_ncb = {1}, a_ncb = {1};
+    if (cols > 16) {
+        s_ncb.push_back(2);
+        a_ncb.push_back(2);
     }
-    if (cand.size() < 2 || budget_seconds == 0.0) return SHT_OK;
-    // scratch input: zero coefficients (the kernels' time does not depend on the values)
+    const std::vector<int> s_mb = {2, 4, 8};
+    // scratch operands: zero coefficients and phases (the kernels' time does
+    // not depend on the values)
     double *alm = nullptr;
-    const size_t bytes = (size_t)p->ntrans * p->ncomp * p->nalm * 16;
-    int rc = dev_alloc((void **)&alm, bytes, "autotune scratch");
+    const size_t abytes = (size_t)p->ntrans * p->ncomp * p->nalm * 16;
+    int rc = dev_alloc((void **)&alm, abytes, "autotune scratch");
     if (rc) return rc;
-    if ((rc = check_hip(hipMemset(alm, 0, bytes), "autotune scratch"))) {
-        dev_free(alm);
-        return rc;
-    }
-    const int orig = p->synth_ncb;
-    int best = orig;
-    double best_ms = 1e300;
+    rc = check_hip(hipMemset(alm, 0, abytes), "autotune scratch");
+    if (!rc) rc = check_hip(hipMemset(p->d_phase, 0, (size_t)p->phase_elems * 16), "autotune scratch");
+    const sht_tuning orig = p->tune;
+    sht_tuning best = orig;
     const auto t_start = std::chrono::steady_clock::now();
-    for (int c : cand) {
-        p->synth_ncb = c;
-        if ((rc = build_synth_items(*p))) break;
+    auto spent = [&] {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    double best_ms = 1e300;
+    for (size_t i = 0; i < s_ncb.size() && !rc; ++i)
+        for (size_t j = 0; j < s_mb.size() && !rc; ++j) {
+            sht_tuning c = best;
+            c.synth_ncb = s_ncb[i];
+            c.synth_mblock = s_mb[j];
+            if (tuning_check(*p, c) != SHT_OK) continue;
+            if ((rc = apply_tuning(*p, c))) break;
+            double ms = 0.0;
+            rc = time_launches([&] { return launch_legendre_synth(*p, alm, p->d_phase, false, nullptr); }, 2, ms);
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+            if (spent() > budget_seconds) break;
+        }
+    best_ms = 1e300;
+    const sht_tuning after_synth = best;
+    for (size_t i = 0; i < a_ncb.size() && !rc; ++i) {
+        sht_tuning c = after_synth;
+        c.anal_ncb = a_ncb[i];
+        c.anal_tpw = anal_tpw_built(p->spin, c.anal_ncb);
+        if (tuning_check(*p, c) != SHT_OK) continue;
+        if ((rc = apply_tuning(*p, c))) break;
         double ms = 0.0;
-        if ((rc = time_synth(*p, alm, 2, ms))) break;
-        if (ms < best_ms) {
+        rc = time_launches([&] { return launch_legendre_anal(*p, p->d_phase, alm, 0, nullptr); }, 2, ms);
+        if (!rc && ms < best_ms) {
             best_ms = ms;
             best = c;
         }
-        const double spent = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-        if (spent > budget_seconds) break;
+        if (spent() > budget_seconds) break;
     }
     dev_free(alm);
-    p->synth_ncb = rc ? orig : best;
-    const int rc2 = build_synth_items(*p);
+    const int rc2 = apply_tuning(*p, rc ? orig : best);
     if (rc) return rc;
     if (rc2) return rc2;
     tune_cache_store(key, best);

@@ -953,6 +953,10 @@ __global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_ana
         const BatchAnaItem bi = items[idx];
         anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(views[bi.plan], bi.m, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], mode, sh);
         __syncthreads();
+        if (bi.m2 >= 0) {
+            anal_item<SPIN, NCB, F32, ana_tpw<SPIN, NCB>()>(views[bi.plan], bi.m2, bi.t0, ptrs.in[bi.plan], ptrs.out[bi.plan], mode, sh);
+            __syncthreads();
+        }
     }
 }
 
@@ -971,6 +975,8 @@ int anal_ncb(int spin, int ntrans)
     int ncb = (cols + 15) / 16;
     return ncb > 2 ? 2 : ncb;
 }
+
+int anal_tpw_built(int spin, int ncb) { return spin ? ana_tpw<2, 1>() : (ncb == 2 ? ana_tpw<0, 2>() : ana_tpw<0, 1>()); }
 
 // default column blocks per synthesis wavefront (the autotuner may change it)
 int synth_ncb_default(int spin, int ntrans, int precision)
@@ -1003,7 +1009,7 @@ template <bool F32>
 static int dispatch_synth(const Plan &p, const LegView &v, const double *alm, double *phase,
                           int deriv, hipStream_t s)
 {
-    const int ncb = p.synth_ncb;
+    const int ncb = p.tune.synth_ncb;
     if (p.spin == 0) {
         if (ncb == 1) launch_synth_t<0, 1, F32>(p, v, alm, phase, 0, s);
         else if (ncb == 2) launch_synth_t<0, 2, F32>(p, v, alm, phase, 0, s);
@@ -1020,7 +1026,7 @@ template <bool F32>
 static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, double *alm,
                           int mode, hipStream_t s)
 {
-    const int ncb = anal_ncb(p.spin, p.ntrans);
+    const int ncb = p.tune.anal_ncb;
     if (p.spin == 0) {
         if (ncb == 1) launch_anal_t<0, 1, F32>(p, v, phase, alm, mode, s);
         else launch_anal_t<0, 2, F32>(p, v, phase, alm, mode, s);
@@ -1038,7 +1044,7 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool 
     const int rc = p.precision == SHT_FP32_MFMA ? dispatch_synth<true>(p, v, alm, phase, d, s)
                                                 : dispatch_synth<false>(p, v, alm, phase, d, s);
     if (rc) {
-        set_error("synthesis column blocks %d not available", p.synth_ncb);
+        set_error("synthesis column blocks %d not available", p.tune.synth_ncb);
         return rc;
     }
     return check_hip(hipGetLastError(), "legendre synthesis launch");

@@ -123,9 +123,9 @@ static void count_work(Plan &p)
 int build_synth_items(Plan &p)
 {
     const int cpj = p.spin ? 4 : 2;
-    const int jpg = p.synth_ncb * 16 / cpj;
+    const int jpg = p.tune.synth_ncb * 16 / cpj;
     const int ngroups = (p.ntrans + jpg - 1) / jpg;
-    constexpr int MB = 4;
+    const int MB = p.tune.synth_mblock;
     std::vector<std::vector<WaveItem>> die(NUM_XCD);
     std::vector<double> load(NUM_XCD, 0.0);
     for (int mb = 0; mb <= p.mmax; mb += MB) {
@@ -226,7 +226,7 @@ static int plan_build(Plan &p)
         if ((rc = dev_alloc((void **)&p.d_dfac, df.size() * sizeof(double), "derivative factors"))) return rc;
         if ((rc = dev_upload(p.d_dfac, df.data(), df.size() * sizeof(double), "upload"))) return rc;
     }
-    p.synth_ncb = synth_ncb_default(p.spin, p.ntrans, p.precision);
+    p.tune = default_tuning(p);
     if ((rc = build_synth_items(p))) return rc;
     p.anal_ms.resize(p.mmax + 1);
     for (int m = 0; m <= p.mmax; ++m) p.anal_ms[m] = m;
@@ -241,6 +241,51 @@ static int plan_build(Plan &p)
 
     if ((rc = fft_plan_build(p))) return rc;
     count_work(p);
+    return SHT_OK;
+}
+
+sht_tuning default_tuning(const Plan &p)
+{
+    sht_tuning t{};
+    t.synth_ncb = synth_ncb_default(p.spin, p.ntrans, p.precision);
+    t.synth_mblock = 4;
+    t.anal_ncb = anal_ncb(p.spin, p.ntrans);
+    t.anal_tpw = anal_tpw_built(p.spin, t.anal_ncb);
+    return t;
+}
+
+int tuning_check(const Plan &p, const sht_tuning &t)
+{
+    if (t.synth_ncb != 1 && t.synth_ncb != 2) {
+        set_error("synth_ncb %d not built (1 or 2)", t.synth_ncb);
+        return SHT_EUNSUPPORTED;
+    }
+    if (t.synth_mblock < 1 || t.synth_mblock > 64) {
+        set_error("synth_mblock %d outside [1, 64]", t.synth_mblock);
+        return SHT_EUNSUPPORTED;
+    }
+    if (t.anal_ncb != 1 && t.anal_ncb != 2) {
+        set_error("anal_ncb %d not built (1 or 2)", t.anal_ncb);
+        return SHT_EUNSUPPORTED;
+    }
+    if (t.anal_tpw != anal_tpw_built(p.spin, t.anal_ncb)) {
+        set_error("anal_tpw %d not built for spin %d and anal_ncb %d", t.anal_tpw, p.spin, t.anal_ncb);
+        return SHT_EUNSUPPORTED;
+    }
+    return SHT_OK;
+}
+
+int apply_tuning(Plan &p, const sht_tuning &t)
+{
+    int rc = tuning_check(p, t);
+    if (rc) return rc;
+    const sht_tuning old = p.tune;
+    p.tune = t;
+    if ((rc = build_synth_items(p))) {
+        p.tune = old;
+        (void)build_synth_items(p);
+        return rc;
+    }
     return SHT_OK;
 }
 
@@ -288,6 +333,30 @@ int check_exec_args(const Plan *p, int direction, const void *in, const void *ou
         return SHT_EDEVICE;
     }
     return SHT_OK;
+}
+
+// The launches of a full transform with the given phase and real-harmonics
+// workspaces (arguments already checked).
+int execute_with(const Plan &pl, int direction, const double *in, double *out, double *phase, double *rh,
+                 hipStream_t s)
+{
+    const Plan *p = &pl;
+    int rc;
+    const int acomp = deriv_direction(direction) ? 1 : p->ncomp;
+    if (synth_direction(direction)) {
+        const double *a = in;
+        if (p->real_h) {
+            if ((rc = launch_real_harm(*p, in, rh, acomp, true, s))) return rc;
+            a = rh;
+        }
+        if ((rc = launch_legendre_synth(*p, a, phase, deriv_direction(direction), s))) return rc;
+        if ((rc = launch_ring_synth(*p, phase, out, weighted_direction(direction), s))) return rc;
+    } else {
+        if ((rc = launch_ring_anal(*p, in, phase, weighted_direction(direction), s))) return rc;
+        if ((rc = launch_legendre_anal(*p, phase, out, anal_mode(direction, p->real_h), s))) return rc;
+        if (p->real_h && (rc = launch_real_harm(*p, out, out, acomp, false, s))) return rc;
+    }
+    return finish_launch("sht_execute");
 }
 
 int finish_launch(const char *what)
@@ -374,22 +443,7 @@ int sht_execute(sht_plan *h, int direction, const double *in, double *out, void 
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     int rc = check_exec_args(p, direction, in, out, false, false);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)hip_stream;
-    const int acomp = deriv_direction(direction) ? 1 : p->ncomp;
-    if (synth_direction(direction)) {
-        const double *a = in;
-        if (p->real_h) {
-            if ((rc = launch_real_harm(*p, in, p->d_rh, acomp, true, s))) return rc;
-            a = p->d_rh;
-        }
-        if ((rc = launch_legendre_synth(*p, a, p->d_phase, deriv_direction(direction), s))) return rc;
-        if ((rc = launch_ring_synth(*p, p->d_phase, out, weighted_direction(direction), s))) return rc;
-    } else {
-        if ((rc = launch_ring_anal(*p, in, p->d_phase, weighted_direction(direction), s))) return rc;
-        if ((rc = launch_legendre_anal(*p, p->d_phase, out, anal_mode(direction, p->real_h), s))) return rc;
-        if (p->real_h && (rc = launch_real_harm(*p, out, out, acomp, false, s))) return rc;
-    }
-    return finish_launch("sht_execute");
+    return execute_with(*p, direction, in, out, p->d_phase, p->d_rh, (hipStream_t)hip_stream);
 }
 
 int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void *hip_stream)
@@ -431,6 +485,24 @@ int sht_ring_fft(sht_plan *h, int direction, const double *in, double *out, void
     }
     if (rc) return rc;
     return finish_launch("sht_ring_fft");
+}
+
+int sht_plan_get_tuning(const sht_plan *h, sht_tuning *t)
+{
+    Plan *p = as_plan(const_cast<sht_plan *>(h));
+    if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
+    if (!t) { set_error("t is NULL"); return SHT_EINVAL; }
+    *t = p->tune;
+    return SHT_OK;
+}
+
+int sht_plan_set_tuning(sht_plan *h, const sht_tuning *t)
+{
+    Plan *p = as_plan(h);
+    if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
+    if (!t) { set_error("t is NULL"); return SHT_EINVAL; }
+    fault_arm();
+    return apply_tuning(*p, *t);
 }
 
 int sht_plan_flops(const sht_plan *h, int direction, double *flops_fp64, double *flops_mfma,

@@ -30,12 +30,13 @@ struct WaveItem {
     int pad;
 };
 
-// Items of the persistent batch analysis kernel (plan index into the batch's tables).
+// Items of the persistent batch analysis kernel (plan index into the batch's
+// tables): one m, or (queue of m pairs) m and m2 = mmax - m one after the other.
 struct BatchAnaItem {
     int plan;
     int m;
     int t0;
-    int pad;
+    int m2;   // second m of the item (-1: none)
 };
 
 // Device-side view of one plan for the Legendre kernels.
@@ -89,7 +90,7 @@ struct Plan {
     std::vector<int> tile_mlim;
     // host-side work lists
     std::vector<WaveItem> synth_items;
-    int synth_ncb = 1;               // column blocks (16 columns) per synthesis item
+    sht_tuning tune{};               // launch shapes (synthesis column blocks, m blocks, ...)
     std::vector<int> anal_ms;
     // device memory
     double *d_slot_cos = nullptr, *d_slot_sin = nullptr, *d_slot_chalf = nullptr,
@@ -138,6 +139,10 @@ struct BatchPtrs {
 
 struct Batch {
     std::vector<Plan *> plans;
+    int queue_order = SHT_QUEUE_COST;    // analysis queue: by cost, or (m, mmax - m) pairs
+    int concurrent = 1;                  // per-plan launch chains on concurrent streams
+    std::vector<hipStream_t> aux;        // one stream per plan (default priority)
+    std::vector<hipEvent_t> join;        // one event per plan, plus the fork event last
     std::vector<uint64_t> plan_serial;   // registry serials of the borrowed plans
     int device = 0;
     int ana_groups = 1;                  // work groups of the persistent analysis launch
@@ -160,6 +165,12 @@ LegView make_leg_view(const Plan &p);
 int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool deriv, hipStream_t s);
 int synth_ncb_default(int spin, int ntrans, int precision);
 int build_synth_items(Plan &p);
+// tuning: defaults for a plan, validity (SHT_OK or SHT_EUNSUPPORTED with a
+// message), and applying one (rebuilds the work lists, bumps the generation)
+sht_tuning default_tuning(const Plan &p);
+int tuning_check(const Plan &p, const sht_tuning &t);
+int apply_tuning(Plan &p, const sht_tuning &t);
+int anal_tpw_built(int spin, int ncb);   // tiles per wavefront of the built analysis kernels
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s);
 
 // persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
@@ -188,5 +199,8 @@ int check_exec_args(const Plan *p, int direction, const void *in, const void *ou
                     bool leg_only);
 Plan *plan_of(sht_plan *h);   // registered plan or nullptr
 int finish_launch(const char *what);
+int execute_with(const Plan &p, int direction, const double *in, double *out, double *phase, double *rh,
+                 hipStream_t s);
+
 
 }  // namespace sht

@@ -125,3 +125,13 @@ def test_hp2048_workload_finite_differences():
     fd, got = _fd_entries(plan1, a, d, grad, ent, h)
     err = np.max(np.abs(fd - got)) / np.max(np.abs(got))
     assert err < 1e-6, err
+    # the backward against the oracle: fac_m Y^T (alm2map(a) - d) on sampled m
+    # of two of the maps
+    resid = to_host(plan.alm2map(a) - d)[[0, 7]]
+    ms = np.array([0, 1, 2, 2048, 4094, 4095])
+    ref = oracle.adjoint_synthesis(g, lmax, lmax, 0, resid, ms=ms)
+    ref = ref * np.where(si.lm_arrays(lmax, lmax)[1] == 0, 1.0, 2.0)[None, None, :, None]
+    sel = np.concatenate([np.arange(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+                          for m in ms])
+    gh = to_host(grad)[[0, 7]]
+    assert rel_err(gh[:, :, sel], ref[:, :, sel]) < 1e-11

@@ -141,6 +141,17 @@ def test_mixed_lmax_workload_batch():
     assert rel_err(to_host(back[0])[:2][:, :, sel], ref_a[:, :, sel]) < TOL64
     # GL quadrature is exact here: the round trip returns the input
     assert rel_err(to_host(back[3]), alms[3]) < 1e-10
+    # the lmax 2047 plan (80% of the work) against the oracle as well
+    g, lmax = geoms[3], 2047
+    rings = np.array([0, 1, 700, 1023, 1024, 2046, 2047])
+    ref = oracle.synthesis(g, lmax, lmax, 0, alms[3][[0, 15]], rings=rings)
+    pix = np.concatenate([np.arange(g.ofs[y], g.ofs[y] + g.nphi[y]) for y in rings])
+    assert rel_err(to_host(maps[3])[[0, 15]][..., pix], ref[..., pix]) < TOL64
+    ms = np.array([0, 1, 2, 1024, 2046, 2047])
+    ref_a = oracle.analysis(g, lmax, lmax, 0, to_host(maps[3])[[0, 15]], ms=ms)
+    sel = np.concatenate([np.arange(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+                          for m in ms])
+    assert rel_err(to_host(back[3])[[0, 15]][:, :, sel], ref_a[:, :, sel]) < TOL64
 
 
 def test_autotune_keeps_results_and_writes_cache(tmp_path):
@@ -162,3 +173,42 @@ def test_autotune_keeps_results_and_writes_cache(tmp_path):
         assert np.array_equal(to_host(p2.alm2map(a)), before)
     finally:
         del os.environ["SHT_TUNE_CACHE"]
+
+
+@pytest.mark.parametrize("order,concurrent", [(1, 1), (0, 0), (1, 0)])
+def test_batch_schedules_give_identical_results(order, concurrent):
+    """Queue of (m, mmax - m) pairs and/or one stream for all plans: the same
+    results bit for bit as the plans' own launches, eager and graph-replayed;
+    the staged batch Legendre step equals the plans' staged steps."""
+    import ctypes
+    import torch
+    sht = _sht()
+    lmaxes = [31, 64, 95]
+    _, plans, alms = _mixed(lmaxes, 5, 0)
+    b = sht.Batch(plans)
+    assert sht.lib.sht_batch_configure(b._h, order, concurrent) == sht.SHT_OK
+    d_alm = [to_dev(a) for a in alms]
+    s = torch.cuda.Stream()
+    for stream in (None, s, s):
+        with torch.cuda.stream(s if stream is not None else torch.cuda.current_stream()):
+            maps = b.alm2map(d_alm, stream=stream)
+            back = b.map2alm(maps, stream=stream)
+        torch.cuda.synchronize()
+        for p, a, mp, ab in zip(plans, d_alm, maps, back):
+            assert np.array_equal(to_host(mp), to_host(p.alm2map(a)))
+            assert np.array_equal(to_host(ab), to_host(p.map2alm(mp)))
+    # staged: Legendre step of the batch
+    F = [torch.empty(p.phase_shape, dtype=torch.float64, device="cuda") for p in plans]
+    a_in = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in d_alm])
+    f_out = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in F])
+    assert sht.lib.sht_batch_legendre(b._h, sht.ALM2MAP, a_in, f_out, None) == sht.SHT_OK
+    torch.cuda.synchronize()
+    for p, a, f in zip(plans, d_alm, F):
+        assert np.array_equal(to_host(f), to_host(p.legendre_synth(a)))
+    out = [torch.empty(p.alm_shape, dtype=torch.float64, device="cuda") for p in plans]
+    o_out = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in out])
+    assert sht.lib.sht_batch_legendre(b._h, sht.MAP2ALM, f_out, o_out, None) == sht.SHT_OK
+    torch.cuda.synchronize()
+    for p, f, o in zip(plans, F, out):
+        assert np.array_equal(to_host(o), to_host(p.legendre_anal(f)))
+    assert sht.lib.sht_batch_configure(b._h, 7, 1) == sht.SHT_EINVAL

@@ -19,6 +19,13 @@ from gpu_util import rel_err, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-11
+# stated bounds of the FP32-MFMA form at the gl4095s2 workload (C_l = 1/(l+1)^2):
+# per degree l, relative to that degree's own power over all m; and per degree
+# over the lowest m only, where the phases G_m carry the power of every degree
+# l >= m, so that their rounding to FP32 (relative u32 = 6e-8 of |G_m|, summed
+# over 4096 rings) is large against the small high-l coefficients
+PER_DEGREE_FP32 = 1e-6
+PER_DEGREE_LOW_M_FP32 = 1e-5
 
 
 def _sht():
@@ -69,10 +76,29 @@ def _sampled_analysis_check(g, lmax, spin, maps_host, alm_host, ms, trans):
     return rel_err(alm_host[trans][:, :, sel], ref[:, :, sel])
 
 
-@pytest.mark.timeout(300)
+def _per_degree_rel(x, ref, lmax, ms=None):
+    """Relative error per degree l: sqrt(sum_m |x - ref|^2 / sum_m |ref|^2) over
+    the stored m (or the sampled ms), all transforms and components."""
+    ls, mm = si.lm_arrays(lmax, lmax)
+    sel = np.ones(ls.shape, bool) if ms is None else np.isin(mm, ms)
+    d2 = np.sum((x - ref) ** 2, axis=(0, 1, 3))[sel]
+    r2 = np.sum(ref ** 2, axis=(0, 1, 3))[sel]
+    num = np.bincount(ls[sel], weights=d2, minlength=lmax + 1)
+    den = np.bincount(ls[sel], weights=r2, minlength=lmax + 1)
+    out = np.zeros(lmax + 1)
+    ok = den > 0
+    out[ok] = np.sqrt(num[ok] / den[ok])
+    return out
+
+
+@pytest.mark.timeout(600)
 def test_gl4095_spin2_workload_sampled():
     """Gauss-Legendre 4096 x 8191, lmax 4095, 16 spin-2 transforms (the
-    benchmark's workload and plan), FP64 and FP32-MFMA."""
+    benchmark's workload and plan), FP64 and FP32-MFMA, both against the
+    oracle on sampled rings and m values: FP64 to 1e-11, the FP32-MFMA form to
+    its stated bound 1e-6 (normwise).  The FP32 form's error per degree is
+    gated too (bound stated with the precision form) and printed for the top
+    64 degrees."""
     sht = _sht()
     lmax = 4095
     g = si.gauss_geometry(4096, 8191)
@@ -83,19 +109,44 @@ def test_gl4095_spin2_workload_sampled():
     mp = p.alm2map(d_a)
     back = to_host(p.map2alm(mp))
     mp_h = to_host(mp)
-    del mp
+    del mp, p
     rings = np.array([0, 1, 1000, 2047, 2048, 3500, 4094, 4095])
     trans = [0, 15]
-    assert _sampled_synthesis_check(g, lmax, 2, a, mp_h, rings, trans) < TOL64
     ms = np.array([0, 1, 2, 3, 1500, 4094, 4095])
-    assert _sampled_analysis_check(g, lmax, 2, mp_h, back, ms, trans) < TOL64
+    ref_map = oracle.synthesis(g, lmax, lmax, 2, np.ascontiguousarray(a[trans]), rings=rings)
+    pix = np.concatenate([np.arange(g.ofs[y], g.ofs[y] + g.nphi[y]) for y in rings])
+    assert rel_err(mp_h[trans][..., pix], ref_map[..., pix]) < TOL64
+    ref_alm = oracle.analysis(g, lmax, lmax, 2, np.ascontiguousarray(mp_h[trans]), ms=ms)
+    sel = np.concatenate([np.arange(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+                          for m in ms])
+    assert rel_err(back[trans][:, :, sel], ref_alm[:, :, sel]) < TOL64
     # GL quadrature is exact for this grid: the round trip returns the input
     assert rel_err(back, a) < 1e-10
+
     p32 = sht.Plan(geom, lmax, spin=2, ntrans=16, precision="fp32_mfma")
     mp32 = to_host(p32.alm2map(d_a))
-    assert rel_err(mp32, mp_h) < 1e-6
     back32 = to_host(p32.map2alm(to_dev(mp_h)))
-    assert rel_err(back32, back) < 1e-6
+    del p32
+    e_map = rel_err(mp32[trans][..., pix], ref_map[..., pix])
+    e_alm = rel_err(back32[trans][:, :, sel], ref_alm[:, :, sel])
+    print(f"\nFP32-MFMA vs oracle (sampled): maps {e_map:.2e}, a_lm {e_alm:.2e}")
+    assert e_map < 1e-6 and e_alm < 1e-6
+    # per ring of the sampled maps (relative to each ring's own amplitude)
+    for y in rings:
+        px = np.arange(g.ofs[y], g.ofs[y] + g.nphi[y])
+        assert rel_err(mp32[trans][..., px], ref_map[..., px]) < 1e-6, y
+    # per degree: against the oracle on the sampled m values, and against the
+    # FP64 result (itself within 1e-11 of the oracle) over every m
+    pd_or = _per_degree_rel(back32[trans], ref_alm, lmax, ms)
+    pd_64 = _per_degree_rel(back32, back, lmax)
+    pd_rt = _per_degree_rel(back32, a, lmax)
+    top = slice(lmax - 63, lmax + 1)
+    print("FP32-MFMA per-degree relative error, l = 4032..4095 (vs FP64, all m): "
+          + " ".join(f"{v:.1e}" for v in pd_64[top]))
+    print(f"FP32-MFMA per-degree max: vs oracle (sampled m) {pd_or[2:].max():.2e}, vs FP64 (all m) "
+          f"{pd_64[2:].max():.2e} at l = {2 + int(np.argmax(pd_64[2:]))}, round trip {pd_rt[2:].max():.2e}")
+    assert pd_64[2:].max() < PER_DEGREE_FP32
+    assert pd_or[2:].max() < PER_DEGREE_LOW_M_FP32
 
 
 def test_healpix1024_workload_sampled():
