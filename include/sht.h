@@ -183,6 +183,23 @@ void sht_plan_destroy(sht_plan *p);
 int sht_execute(sht_plan *p, int direction, const double *in, double *out,
                 void *hip_stream);
 
+/* Allocation-free form of sht_execute, for callers that cannot allocate device
+   memory while they run: work captured into a HIP graph, tight serving loops,
+   harnesses that forbid allocation.  Same arguments, directions and results
+   (bit for bit) as sht_execute; the plan's phase workspace (and, with
+   real_harmonics, its coefficient workspace) is replaced by a static device
+   array of the library of 64 MiB per device (sht_noalloc_capacity), which each
+   device holds from the first plan creation on it until the process ends.
+   The call allocates nothing.  SHT_EINVAL when the plan needs more workspace
+   than that (ntrans * ncomp * nrings * (mmax + 1) * 16 bytes of phases, plus
+   ntrans * ncomp * nalm * 16 with real_harmonics).  Every call on one device
+   shares that device's array: calls that overlap in time on one device (on
+   streams not ordered with each other) race and give undefined results. */
+int sht_execute_noalloc(sht_plan *p, int direction, const double *in, double *out,
+                        void *hip_stream);
+/* Bytes of the static workspace of sht_execute_noalloc. */
+int sht_noalloc_capacity(int64_t *bytes);
+
 /* Legendre step only (Eqs. 4, 5).  SHT_ALM2MAP (and SHT_MAP2ALM_ADJOINT, the
    same Legendre step): in = a_lm, out = F phases; SHT_ALM2MAP_DERIV1: in =
    spin-0 a_lm, out = F phases of the derivative maps.

@@ -81,6 +81,8 @@ _sig("sht_plan_create", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_
      ctypes.c_int, ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp))
 _sig("sht_plan_destroy", None, _vp)
 _sig("sht_execute", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
+_sig("sht_execute_noalloc", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
+_sig("sht_noalloc_capacity", ctypes.c_int, _i64p)
 _sig("sht_legendre", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
 _sig("sht_ring_fft", ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp)
 _sig("sht_plan_flops", ctypes.c_int, _vp, ctypes.c_int, _dp, _dp, _dp)
@@ -119,6 +121,13 @@ def memory_stats():
     n, b = ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.sht_memory_stats(ctypes.byref(n), ctypes.byref(b)))
     return n.value, b.value
+
+
+def noalloc_capacity() -> int:
+    """Bytes of the static workspace of the allocation-free entry point."""
+    b = ctypes.c_int64()
+    _check(_lib.sht_noalloc_capacity(ctypes.byref(b)))
+    return b.value
 
 
 def nalm(lmax: int, mmax: int) -> int:
@@ -305,6 +314,12 @@ class Plan:
     def alm2map_deriv1_grad(self, grad_maps, stream=None, out=None):
         """Gradient of a real loss with respect to the a_lm of alm2map_deriv1."""
         return self._run(_lib.sht_execute, ALM2MAP_DERIV1_GRAD, grad_maps, self.deriv_alm_shape, stream, out)
+
+    def execute_noalloc(self, direction, x, stream=None, out=None):
+        """sht_execute without any device allocation: the workspace is the
+        library's static per-device array (out must then be given by callers
+        that cannot allocate)."""
+        return self._run(_lib.sht_execute_noalloc, direction, x, self.out_shape(direction), stream, out)
 
     def legendre_synth(self, alm, stream=None, out=None):
         return self._run(_lib.sht_legendre, ALM2MAP, alm, self.phase_shape, stream, out)

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsht.so")
 
-SOURCES = ["host.cpp", "sht_api.cpp", "legendre.hip", "ringfft.hip", "realharm.hip", "batch.cpp"]
+SOURCES = ["host.cpp", "sht_api.cpp", "legendre.hip", "ringfft.hip", "realharm.hip", "batch.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -403,6 +403,9 @@ int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans,
         return SHT_EDEVICE;
     }
 
+    // set-up of the allocation-free entry point on this device (its failure
+    // only disables that entry point)
+    if (scratch_init(dev) != SHT_OK) set_error("");
     Plan *p = new (std::nothrow) Plan();
     if (!p) { set_error("host allocation failed"); return SHT_ENOMEM; }
     p->device = dev;

@@ -201,6 +201,10 @@ Plan *plan_of(sht_plan *h);   // registered plan or nullptr
 int finish_launch(const char *what);
 int execute_with(const Plan &p, int direction, const double *in, double *out, double *phase, double *rh,
                  hipStream_t s);
-
+// bytes of the workspaces of one full transform (phases, real-harmonics coefficients)
+size_t exec_workspace_bytes(const Plan &p, size_t *rh_offset);
+// static device scratch of the allocation-free entry point (noalloc.hip):
+// resolves its address on the device (once per device)
+int scratch_init(int device);
 
 }  // namespace sht
