@@ -98,7 +98,7 @@ _sig("sht_autotune", ctypes.c_int, _vp, ctypes.c_double)
 
 class Tuning(ctypes.Structure):
     _fields_ = [("synth_ncb", ctypes.c_int), ("synth_mblock", ctypes.c_int), ("anal_ncb", ctypes.c_int),
-                ("anal_tpw", ctypes.c_int), ("reserved", ctypes.c_int * 12)]
+                ("anal_tpw", ctypes.c_int), ("valu", ctypes.c_int), ("reserved", ctypes.c_int * 11)]
 
 
 _sig("sht_plan_get_tuning", ctypes.c_int, _vp, ctypes.POINTER(Tuning))
@@ -350,7 +350,7 @@ class Plan:
     def autotune(self, budget_seconds: float = 0.1):
         _check(_lib.sht_autotune(self._h, budget_seconds))
 
-    _TUNING_KEYS = ("synth_ncb", "synth_mblock", "anal_ncb", "anal_tpw")
+    _TUNING_KEYS = ("synth_ncb", "synth_mblock", "anal_ncb", "anal_tpw", "valu")
 
     def tuning(self) -> dict:
         t = Tuning()

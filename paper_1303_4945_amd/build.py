@@ -27,10 +27,10 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-Wno-u
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON
-    # every source is compiled as HIP for gfx950 only (the .cpp files hold host
-    # code and no kernels; without the target hipcc would also build a device
-    # pass for its default architecture)
-    cmd += ["-x", "hip"] + DEVICE_FLAGS
+    # every source is compiled (hipcc treats .cpp as HIP) for gfx950 only: the
+    # .cpp files hold host code and no kernels, and without the target hipcc
+    # would also build a device pass for its default architecture
+    cmd += DEVICE_FLAGS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile {src} failed:\n{r.stdout}\n{r.stderr}")

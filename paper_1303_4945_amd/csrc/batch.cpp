@@ -131,7 +131,16 @@ int batch_legendre_anal(Batch &b, int direction, const double *const *phase, dou
         ptrs.out[i] = out[i];
     }
     int rc;
-    if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction, b.real_h), s))) return rc;
+    bool valu = false;
+    for (const Plan *p : b.plans) valu = valu || p->tune.valu;
+    if (valu) {
+        // plans on the vector-unit path: each plan's own analysis launch (the
+        // persistent queue runs the matrix-core kernels), same results as the plans
+        for (int i = 0; i < np; ++i)
+            if ((rc = launch_legendre_anal(*b.plans[i], phase[i], out[i], anal_mode(direction, b.real_h), s))) return rc;
+    } else if ((rc = launch_legendre_anal_batch(b, ptrs, anal_mode(direction, b.real_h), s))) {
+        return rc;
+    }
     if (b.real_h)
         for (int i = 0; i < np; ++i)
             if ((rc = launch_real_harm(*b.plans[i], out[i], out[i], deriv_direction(direction) ? 1 : b.plans[i]->ncomp,
@@ -215,17 +224,17 @@ std::string tune_key(const Plan &p)
 
 std::string tune_text(const sht_tuning &t)
 {
-    char buf[128];
-    std::snprintf(buf, sizeof buf, "synth_ncb=%d,synth_mblock=%d,anal_ncb=%d,anal_tpw=%d", t.synth_ncb,
-                  t.synth_mblock, t.anal_ncb, t.anal_tpw);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "synth_ncb=%d,synth_mblock=%d,anal_ncb=%d,anal_tpw=%d,valu=%d", t.synth_ncb,
+                  t.synth_mblock, t.anal_ncb, t.anal_tpw, t.valu);
     return buf;
 }
 
 bool tune_parse(const char *s, sht_tuning &t)
 {
     sht_tuning r{};
-    if (std::sscanf(s, "synth_ncb=%d,synth_mblock=%d,anal_ncb=%d,anal_tpw=%d", &r.synth_ncb, &r.synth_mblock,
-                    &r.anal_ncb, &r.anal_tpw) != 4)
+    if (std::sscanf(s, "synth_ncb=%d,synth_mblock=%d,anal_ncb=%d,anal_tpw=%d,valu=%d", &r.synth_ncb,
+                    &r.synth_mblock, &r.anal_ncb, &r.anal_tpw, &r.valu) != 5)
         return false;
     t = r;
     return true;
@@ -477,6 +486,7 @@ int sht_autotune(sht_plan *h, double budget_seconds)
     if (!rc) rc = check_hip(hipMemset(p->d_phase, 0, (size_t)p->phase_elems * 16), "autotune scratch");
     const sht_tuning orig = p->tune;
     sht_tuning best = orig;
+    best.valu = 0;   // the matrix-core knobs first, then the vector path against them
     const auto t_start = std::chrono::steady_clock::now();
     auto spent = [&] {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -512,6 +522,21 @@ int sht_autotune(sht_plan *h, double budget_seconds)
             best = c;
         }
         if (spent() > budget_seconds) break;
+    }
+    // vector-unit kernels (spin 0, FP64) against the best matrix-core shape,
+    // on the time of one synthesis plus one analysis
+    if (!rc && p->spin == 0 && p->precision == SHT_FP64) {
+        double pair_ms[2] = {1e300, 1e300};
+        for (int vv = 0; vv < 2 && !rc; ++vv) {
+            sht_tuning c = best;
+            c.valu = vv;
+            if ((rc = apply_tuning(*p, c))) break;
+            double ms1 = 0.0, ms2 = 0.0;
+            rc = time_launches([&] { return launch_legendre_synth(*p, alm, p->d_phase, false, nullptr); }, 2, ms1);
+            if (!rc) rc = time_launches([&] { return launch_legendre_anal(*p, p->d_phase, alm, 0, nullptr); }, 2, ms2);
+            pair_ms[vv] = ms1 + ms2;
+        }
+        if (!rc) best.valu = pair_ms[1] < pair_ms[0] ? 1 : 0;
     }
     dev_free(alm);
     const int rc2 = apply_tuning(*p, rc ? orig : best);

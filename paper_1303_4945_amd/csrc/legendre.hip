@@ -960,6 +960,325 @@ __global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_ana
     }
 }
 
+// ---------------------------------------------------------------- vector path
+//
+// For a few simultaneous spin-0 transforms most matrix-core columns would be
+// empty (2 of 16 for one transform), so the products run on the vector units
+// instead, with no empty columns: every FMA is one of the algorithm's
+// (Sect. 3.2's loop nests, one ring slot per lane).
+//   synthesis: lane = slot; per degree the recursion's two FMAs and, per
+//     transform, two FMAs with c f_l a_lm broadcast from LDS into the slot's
+//     even and odd class accumulators (no reduction at all);
+//   analysis: the recursion (lane = slot) writes a chunk of mu_l to LDS; the
+//     products then run transposed, lane = degree (and half of the slots):
+//     every lane sums its degree over the slots of the tile against the
+//     stationary phases G_t +- G_(pi-t) broadcast from LDS, so no cross-lane
+//     reduction per degree is needed; the two slot halves are added once per
+//     chunk, and the wavefronts' partial sums in a fixed order (deterministic).
+
+// One recursion chunk of LC degrees (chains of a wave as in chain_chunk),
+// calling emit(t, value) for each degree offset t with value = mu_l (0 outside
+// [l0, lmax] and while the lane's scale k < 0).
+template <int LC, typename Emit>
+__device__ __forceinline__ void chain_chunk_emit(Chain &c, const double4 *__restrict__ cf, bool diff, bool &slow,
+                                                 int l0, int lc, int lmax, double thr, double down, Emit emit)
+{
+    if (!slow && lc >= l0 && lc + LC <= lmax) {
+        if (diff) {
+#pragma unroll 4
+            for (int t = 0; t < LC; ++t) {
+                const double4 q = cf[t];
+                emit(t, c.mu);
+                const double eps = fma(q.x, c.ms2, q.z);
+                c.aux = fma(eps, c.mu, c.aux);
+                c.mu += c.aux;
+            }
+        } else {
+#pragma unroll 4
+            for (int t = 0; t < LC; ++t) {
+                const double4 q = cf[t];
+                emit(t, c.mu);
+                const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
+                c.aux = c.mu;
+                c.mu = nx;
+            }
+        }
+        return;
+    }
+#pragma unroll 4
+    for (int t = 0; t < LC; ++t) {
+        const int l = lc + t;
+        emit(t, (l >= l0 && l <= lmax && c.k == 0) ? c.mu : 0.0);
+        if (l >= l0 && l < lmax) {
+            const double4 q = cf[t];
+            if (diff) {
+                const double eps = fma(q.x, c.ms2, q.z);
+                c.aux = fma(eps, c.mu, c.aux);
+                c.mu += c.aux;
+            } else {
+                const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
+                c.aux = c.mu;
+                c.mu = nx;
+            }
+            if (c.k < 0 && fabs(c.mu) >= thr) {
+                c.mu *= down;
+                c.aux *= down;
+                c.k += 1;
+            }
+        }
+    }
+    slow = wave_any(c.k < 0);
+}
+
+template <int J>
+struct SynValuShared {
+    double4 cfs[2][SYN_LC];          // step coefficients of two chunks
+    double2 co[2][SYN_LC][J];        // c f_l a_lm of the chunk's degrees, per transform
+};
+
+// Work item (m, 64-slot tile, J transforms from t0), one wavefront.
+template <int J>
+__global__ __launch_bounds__(64) void k_legendre_synth_valu(LegView v, const WaveItem *__restrict__ items,
+                                                            const double *__restrict__ alm,
+                                                            double *__restrict__ phase)
+{
+    constexpr int LC = SYN_LC;
+    __shared__ SynValuShared<J> sh;
+    const WaveItem it = items[blockIdx.x];
+    if (it.m < 0) return;
+    const int lane = threadIdx.x;
+    const int m = it.m, tile = it.tile, t0 = it.t0, lmax = v.lmax;
+    const int l0 = m;   // spin 0: l0 + m even, the first chunk starts at l0
+    const double4 *coef = v.coef + v.coef_ofs[m];
+    const double *flm = v.fl + v.coef_ofs[m];
+    const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
+    const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
+    Chain cs = chain_init(v, m, tile * 64 + lane, 0);
+    const bool diff = wave_any(cs.x > DIFF_FORM_COS);
+    if (diff) cs.aux = cs.mu;
+    bool slow = wave_any(cs.k < 0);
+
+    // the chunk's step coefficients and c f_l a_lm (zero outside [l0, lmax], for
+    // absent transforms and for Im at m = 0: ignored entries never reach the sums)
+    auto stage = [&](int buf, int lc) {
+        if (lane < LC) {
+            const int l = lc + lane;
+            const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
+            sh.cfs[buf][lane] = chain_coef(c, false, 0.0);
+        }
+        for (int e = lane; e < LC * J; e += 64) {
+            const int t = e / J, tr = e % J;
+            const int l = lc + t;
+            double2 a = make_double2(0.0, 0.0);
+            if (l <= lmax && t0 + tr < v.ntrans) {
+                const double f = flm[l];
+                const double *ap = alm + ((int64_t)(t0 + tr) * v.nalm + mbase + l) * 2;
+                a = make_double2(ap[0] * f, m == 0 ? 0.0 : ap[1] * f);
+            }
+            sh.co[buf][t][tr] = a;
+        }
+    };
+
+    double2 acc[2][J];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int tr = 0; tr < J; ++tr) acc[p][tr] = make_double2(0.0, 0.0);
+    stage(0, l0);
+    wave_sync();
+    int chunk = 0;
+    for (int lc = l0; lc <= lmax; lc += LC, ++chunk) {
+        const int buf = chunk & 1;
+        if (lc + LC <= lmax) stage(buf ^ 1, lc + LC);
+        chain_chunk_emit<LC>(cs, sh.cfs[buf], diff, slow, l0, lc, lmax, thr, down, [&](int t, double mu) {
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) {
+                const double2 a = sh.co[buf][t][tr];
+                acc[t & 1][tr].x = fma(mu, a.x, acc[t & 1][tr].x);
+                acc[t & 1][tr].y = fma(mu, a.y, acc[t & 1][tr].y);
+            }
+        });
+        wave_sync();
+    }
+    // ring t = A0 + A1, ring pi - t = A0 - A1
+    const int slot = tile * 64 + lane;
+    if (slot >= v.nslots) return;
+    const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
+    double2 *ph = reinterpret_cast<double2 *>(phase);
+#pragma unroll
+    for (int tr = 0; tr < J; ++tr) {
+        const int t = t0 + tr;
+        if (t >= v.ntrans) break;
+        const int64_t rowbase = (int64_t)t * v.nrings;
+        const double2 a0 = acc[0][tr], a1 = acc[1][tr];
+        if (yn >= 0) ph[(rowbase + yn) * (v.mmax + 1) + m] = make_double2(a0.x + a1.x, a0.y + a1.y);
+        if (ys >= 0) ph[(rowbase + ys) * (v.mmax + 1) + m] = make_double2(a0.x - a1.x, a0.y - a1.y);
+    }
+}
+
+// wavefronts per analysis work group (vector path; eight for one transform,
+// one work group per CU, measured slower)
+template <int J>
+constexpr int anv_nw() { return 4; }
+constexpr int ANV_LC = 32;   // degrees per chunk
+constexpr int ANV_ROW = 65;  // LDS row of mu: 64 slots (+ pad)
+
+template <int J>
+struct AnaValuShared {
+    static constexpr int NW = anv_nw<J>();
+    double lam[NW][ANV_LC][ANV_ROW];       // mu of the wavefront's tile, [degree][slot]
+    double2 g[NW][2][64][J];               // its stationary phases: class, slot, transform
+    double2 part[NW][ANV_LC][J];           // its partial sums of the chunk
+    double4 cfs[2][ANV_LC];                // step coefficients, staged one chunk ahead
+    double fls[2][ANV_LC];                 // f_l of the chunk's degrees
+};
+
+// Work group = one m and J transforms from blockIdx.y J; the m's active tiles
+// are taken anv_nw at a time (one per wavefront), and every pass reads and
+// writes the m's a_lm row once.
+template <int J>
+__global__ __launch_bounds__(64 * anv_nw<J>()) void k_legendre_anal_valu(LegView v, const int *__restrict__ mlist,
+                                                                    const double *__restrict__ phase,
+                                                                    double *__restrict__ alm, int mode)
+{
+    constexpr int LC = ANV_LC, NW = anv_nw<J>(), NT = 64 * NW;
+    __shared__ AnaValuShared<J> sh;
+    const int m = mlist[blockIdx.x];
+    const int t0 = (int)blockIdx.y * J;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lmax = v.lmax;
+    const int l0 = m;
+    const double4 *coef = v.coef + v.coef_ofs[m];
+    const double *flm = v.fl + v.coef_ofs[m];
+    const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
+    const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
+    const bool grad = mode & ANA_MODE_GRAD;
+    const double2 *G = reinterpret_cast<const double2 *>(phase);
+    double2 *out = reinterpret_cast<double2 *>(alm);
+
+    auto stage = [&](int buf, int lc) {   // wavefront 0
+        if (lane < LC) {
+            const int l = lc + lane;
+            const int lcl = l > lmax ? lmax : l;
+            const double4 c = (l < lmax) ? coef[lcl] : double4{0, 0, 0, 0};
+            sh.cfs[buf][lane] = chain_coef(c, false, 0.0);
+            sh.fls[buf][lane] = (l <= lmax) ? flm[lcl] : 0.0;
+        }
+    };
+    int ntiles_act = 0;
+    for (int t = 0; t < v.ntiles; ++t) ntiles_act += v.tile_mlim[t] >= m;
+    int tscan = 0, tcount = 0;
+    bool first = true;
+    while (tcount < ntiles_act || first) {
+        // this pass's tile of this wavefront (-1: none)
+        int ptile = -1;
+        {
+            int k = 0;
+            for (; tscan < v.ntiles && k < NW; ++tscan) {
+                if (v.tile_mlim[tscan] < m) continue;
+                if (k == wave) ptile = tscan;
+                ++k;
+            }
+            tcount += k;
+        }
+        // stationary phases G_t +- G_(pi-t) of the tile's slots (zero for
+        // missing rings, absent transforms and when the wavefront has no tile)
+        Chain cs = chain_init(v, m, ptile >= 0 ? ptile * 64 + lane : v.nslots, 0);
+        const bool diff = wave_any(cs.x > DIFF_FORM_COS);
+        if (diff) cs.aux = cs.mu;
+        bool slow = wave_any(cs.k < 0);
+        {
+            const int slot = ptile >= 0 ? ptile * 64 + lane : v.nslots;
+            const bool ok = slot < v.nslots;
+            const int yn = ok ? v.slot_yn[slot] : -1, ys = ok ? v.slot_ys[slot] : -1;
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) {
+                const bool tok = t0 + tr < v.ntrans;
+                const int64_t rowbase = (int64_t)(tok ? t0 + tr : 0) * v.nrings;
+                const double2 gn0 = G[(rowbase + (yn >= 0 ? yn : 0)) * (v.mmax + 1) + m];
+                const double2 gs0 = G[(rowbase + (ys >= 0 ? ys : 0)) * (v.mmax + 1) + m];
+                const double2 gn = (tok && yn >= 0) ? gn0 : make_double2(0.0, 0.0);
+                const double2 gs = (tok && ys >= 0) ? gs0 : make_double2(0.0, 0.0);
+                sh.g[wave][0][lane][tr] = make_double2(gn.x + gs.x, gn.y + gs.y);
+                sh.g[wave][1][lane][tr] = make_double2(gn.x - gs.x, gn.y - gs.y);
+            }
+        }
+        if (wave == 0) stage(0, l0);
+        __syncthreads();
+        int chunk = 0;
+        for (int lc = l0; lc <= lmax; lc += LC, ++chunk) {
+            const int buf = chunk & 1;
+            // the previous passes' sums of this thread's output element (if it
+            // has one), loaded now so that the load is in flight during the
+            // recursion and the products
+            double2 prev = make_double2(0.0, 0.0);
+            if (!first && tid < LC * J) {
+                const int td = tid / J, tr = tid % J;
+                const int l = lc + td;
+                if (l <= lmax && t0 + tr < v.ntrans) prev = out[(int64_t)(t0 + tr) * v.nalm + mbase + l];
+            }
+            // the recursion of the tile, mu to LDS (lane = slot)
+            double *lw = &sh.lam[wave][0][0];
+            if (ptile >= 0)
+                chain_chunk_emit<LC>(cs, sh.cfs[buf], diff, slow, l0, lc, lmax, thr, down,
+                                     [&](int t, double mu) { lw[t * ANV_ROW + lane] = mu; });
+            wave_sync();
+            // products, lane = degree t and slot part h (64 / LC parts of LC slots)
+            constexpr int PS = LC;   // slots per part
+            const int t = lane & (LC - 1), h = lane / LC;
+            double2 sacc[J];
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) sacc[tr] = make_double2(0.0, 0.0);
+            if (ptile >= 0) {
+                const int cls = t & 1;
+                const double *row = lw + t * ANV_ROW + h * PS;
+#pragma unroll 8
+                for (int k = 0; k < PS; ++k) {
+                    const double lv = row[k];
+#pragma unroll
+                    for (int tr = 0; tr < J; ++tr) {
+                        const double2 gv = sh.g[wave][cls][h * PS + k][tr];
+                        sacc[tr].x = fma(lv, gv.x, sacc[tr].x);
+                        sacc[tr].y = fma(lv, gv.y, sacc[tr].y);
+                    }
+                }
+            }
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) {
+#pragma unroll
+                for (int off = LC; off < 64; off *= 2) {
+                    sacc[tr].x += __shfl_xor(sacc[tr].x, off);
+                    sacc[tr].y += __shfl_xor(sacc[tr].y, off);
+                }
+                if (lane < LC) sh.part[wave][lane][tr] = sacc[tr];
+            }
+            if (wave == 0 && lc + LC <= lmax) stage(buf ^ 1, lc + LC);
+            __syncthreads();
+            // the wavefronts' sums in a fixed order, times f_l (and fac_m), into a_lm
+            static_assert(LC * J <= NT, "one output element per thread");
+            if (tid < LC * J) {
+                const int td = tid / J, tr = tid % J;
+                const int l = lc + td;
+                if (l <= lmax && t0 + tr < v.ntrans) {
+                    double2 sum = sh.part[0][td][tr];
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) {
+                        sum.x += sh.part[w][td][tr].x;
+                        sum.y += sh.part[w][td][tr].y;
+                    }
+                    double f = sh.fls[buf][td];
+                    if (grad && m > 0) f *= 2.0;   // fac_m of the real-field gradient
+                    sum = make_double2(sum.x * f, m == 0 ? 0.0 : sum.y * f);
+                    if (!first) sum = make_double2(prev.x + sum.x, prev.y + sum.y);
+                    out[(int64_t)(t0 + tr) * v.nalm + mbase + l] = sum;
+                }
+            }
+            __syncthreads();
+        }
+        first = false;
+    }
+}
+
 __global__ void k_reset_counter(unsigned *counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
@@ -1036,10 +1355,20 @@ static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, 
     }
 }
 
+int valu_jpg(const Plan &p) { return p.ntrans >= 2 ? 2 : 1; }
+
 int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool deriv, hipStream_t s)
 {
     if (p.synth_items.empty()) return SHT_OK;
     const LegView v = make_leg_view(p);
+    if (p.tune.valu) {
+        const dim3 grid((unsigned)p.synth_items.size());
+        if (valu_jpg(p) == 1)
+            hipLaunchKernelGGL(k_legendre_synth_valu<1>, grid, dim3(64), 0, s, v, p.d_synth_items, alm, phase);
+        else
+            hipLaunchKernelGGL(k_legendre_synth_valu<2>, grid, dim3(64), 0, s, v, p.d_synth_items, alm, phase);
+        return check_hip(hipGetLastError(), "legendre synthesis launch");
+    }
     const int d = deriv ? 1 : 0;
     const int rc = p.precision == SHT_FP32_MFMA ? dispatch_synth<true>(p, v, alm, phase, d, s)
                                                 : dispatch_synth<false>(p, v, alm, phase, d, s);
@@ -1053,6 +1382,17 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool 
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s)
 {
     const LegView v = make_leg_view(p);
+    if (p.tune.valu) {
+        const int j = valu_jpg(p);
+        const dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + j - 1) / j));
+        if (j == 1)
+            hipLaunchKernelGGL(k_legendre_anal_valu<1>, grid, dim3(64 * anv_nw<1>()), 0, s, v, p.d_anal_ms, phase, alm,
+                               mode);
+        else
+            hipLaunchKernelGGL(k_legendre_anal_valu<2>, grid, dim3(64 * anv_nw<2>()), 0, s, v, p.d_anal_ms, phase, alm,
+                               mode);
+        return check_hip(hipGetLastError(), "legendre analysis launch");
+    }
     if (p.precision == SHT_FP32_MFMA) dispatch_anal<true>(p, v, phase, alm, mode, s);
     else dispatch_anal<false>(p, v, phase, alm, mode, s);
     return check_hip(hipGetLastError(), "legendre analysis launch");

@@ -123,7 +123,7 @@ static void count_work(Plan &p)
 int build_synth_items(Plan &p)
 {
     const int cpj = p.spin ? 4 : 2;
-    const int jpg = p.tune.synth_ncb * 16 / cpj;
+    const int jpg = p.tune.valu ? valu_jpg(p) : p.tune.synth_ncb * 16 / cpj;
     const int ngroups = (p.ntrans + jpg - 1) / jpg;
     const int MB = p.tune.synth_mblock;
     std::vector<std::vector<WaveItem>> die(NUM_XCD);
@@ -251,6 +251,7 @@ sht_tuning default_tuning(const Plan &p)
     t.synth_mblock = 4;
     t.anal_ncb = anal_ncb(p.spin, p.ntrans);
     t.anal_tpw = anal_tpw_built(p.spin, t.anal_ncb);
+    t.valu = (p.spin == 0 && p.precision == SHT_FP64 && p.ntrans <= 2) ? 1 : 0;
     return t;
 }
 
@@ -266,6 +267,14 @@ int tuning_check(const Plan &p, const sht_tuning &t)
     }
     if (t.anal_ncb != 1 && t.anal_ncb != 2) {
         set_error("anal_ncb %d not built (1 or 2)", t.anal_ncb);
+        return SHT_EUNSUPPORTED;
+    }
+    if (t.valu != 0 && t.valu != 1) {
+        set_error("valu must be 0 or 1");
+        return SHT_EUNSUPPORTED;
+    }
+    if (t.valu && (p.spin != 0 || p.precision != SHT_FP64)) {
+        set_error("the vector-unit kernels are built for spin 0 and SHT_FP64 only");
         return SHT_EUNSUPPORTED;
     }
     if (t.anal_tpw != anal_tpw_built(p.spin, t.anal_ncb)) {

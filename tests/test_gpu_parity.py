@@ -37,24 +37,31 @@ CASES = {
     "gl_odd_nphi_prime": (lambda: si.gauss_geometry(40, 79), 39, 39, 0, 2),
     "gl_s2_j16": (lambda: si.gauss_geometry(16, 31), 15, 15, 2, 16),
     # ring lengths of every FFT kind: 8191 prime with 8190 = 2 3^2 5 7 13
-    # (paired, Rader), 16382 (half length 8191, Rader), 8190 (half 4095 =
-    # 3^2 5 7 13, direct), 1287 = 3^2 11 13 (paired, direct odd radices), 2006
-    # (half 1003 = 17 59, Bluestein in LDS), 4097 = 17 241 (paired, Bluestein
-    # split in two halves), 257 (prime, Rader with a power-of-two inner length),
-    # 4096 (half 2048, radix 8/4/2)
-    "fft_lengths_s2": (lambda: si.mixed_geometry([8191, 16382, 8190, 1287, 2006], 0.2),
+    # (paired, no aliasing: Rader with the convolution split into two halves
+    # of 4095), 7351 (prime, split Rader with 3675 = 3 5^2 7^2), 4051 (prime,
+    # split Rader with 2025 = 3^4 5^2), 16382 (half length 8191, Rader), 8190
+    # (half 4095 = 3^2 5 7 13, direct), 1287 = 3^2 11 13 (paired, direct odd
+    # radices), 2006 (half 1003 = 17 59, Bluestein in LDS), 4097 = 17 241
+    # (paired, Bluestein split in two halves), 257 (prime, Rader with a
+    # power-of-two inner length), 4096 (half 2048, radix 8/4/2)
+    "fft_lengths_s2": (lambda: si.mixed_geometry([8191, 16382, 8190, 1287, 2006, 7351], 0.2),
                        60, 60, 2, 2),
-    "fft_lengths_s0": (lambda: si.mixed_geometry([4097, 1287, 257, 2006, 4096, 8191], 0.37),
+    "fft_lengths_s0": (lambda: si.mixed_geometry([4097, 1287, 257, 2006, 4096, 8191, 4051], 0.37),
                        45, 40, 0, 3),
+    # 8191 and 4051 with mmax above half the ring length (aliased terms): the
+    # unsplit Rader form over the whole length
+    # (no polar skipping: the staged phases of the terms it drops would be zero)
+    "fft_rader_alias": (lambda: si.mixed_geometry([8191, 4051], 0.1), 4200, 4200, 0, 1, {"polar": False}),
 }
 
 
 def _setup(name, precision="fp64"):
     sht = _sht()
-    build, lmax, mmax, spin, ntrans = CASES[name]
+    build, lmax, mmax, spin, ntrans = CASES[name][:5]
+    kw = CASES[name][5] if len(CASES[name]) > 5 else {}
     g = build()
     geom = sht.Geometry.from_inputs(g)
-    plan = sht.Plan(geom, lmax, mmax, spin=spin, ntrans=ntrans, precision=precision)
+    plan = sht.Plan(geom, lmax, mmax, spin=spin, ntrans=ntrans, precision=precision, **kw)
     a = si.random_alm(lmax, mmax, ntrans, spin, tag=zlib.crc32(name.encode()) % 1000)
     return g, plan, a
 

@@ -1,0 +1,83 @@
+"""The vector-unit Legendre kernels (spin 0, one or two transforms: the
+default there) against the oracle and against the matrix-core kernels of the
+same plan (set through the tuning), including the gradient mode, batches and
+ragged sizes."""
+import numpy as np
+import pytest
+
+import oracle
+import sht_inputs as si
+from gpu_util import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def _sht():
+    import paper_1303_4945_amd as sht
+    return sht
+
+
+CASES = {
+    # name: (geometry, lmax, mmax, ntrans)
+    "gl_j1": (lambda: si.gauss_geometry(48, 95, 0.2), 47, 47, 1),
+    "gl_j2_mmax": (lambda: si.gauss_geometry(40, 81), 39, 25, 2),
+    "hp_j1_alias": (lambda: si.healpix_geometry(16), 47, 47, 1),
+    "hp_j3_ragged": (lambda: si.healpix_geometry(8), 23, 23, 3),   # groups of two, the last one ragged
+    "gl_lmax0": (lambda: si.gauss_geometry(1, 1), 0, 0, 1),
+    "gl_j1_long": (lambda: si.gauss_geometry(200, 399), 199, 199, 1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_valu_against_oracle_and_matrix_path(name):
+    sht = _sht()
+    build, lmax, mmax, ntrans = CASES[name]
+    g = build()
+    p = sht.Plan(sht.Geometry.from_inputs(g), lmax, mmax, spin=0, ntrans=ntrans)
+    if ntrans <= 2:
+        assert p.tuning()["valu"] == 1, "the vector path is the default for one or two transforms"
+    p.set_tuning(valu=1)
+    a = si.random_alm(lmax, mmax, ntrans, 0, tag=17)
+    d_a = to_dev(a)
+    mp = to_host(p.alm2map(d_a))
+    ref_map = oracle.synthesis(g, lmax, mmax, 0, a)
+    assert rel_err(mp, ref_map) < TOL64
+    back = to_host(p.map2alm(to_dev(ref_map)))
+    ref_alm = oracle.analysis(g, lmax, mmax, 0, ref_map)
+    assert rel_err(back, ref_alm) < TOL64
+    grad = to_host(p.alm2map_grad(to_dev(ref_map)))
+    ref_g = oracle.adjoint_synthesis(g, lmax, mmax, 0, ref_map)
+    ref_g = ref_g * np.where(si.lm_arrays(lmax, mmax)[1] == 0, 1.0, 2.0)[None, None, :, None]
+    assert rel_err(grad, ref_g) < TOL64
+    # the matrix-core kernels give the same sums up to rounding order
+    p.set_tuning(valu=0)
+    assert rel_err(to_host(p.alm2map(d_a)), mp) < 1e-13
+    assert rel_err(to_host(p.map2alm(to_dev(ref_map))), back) < 1e-13
+
+
+def test_valu_batch_equals_plans():
+    sht = _sht()
+    plans, alms = [], []
+    for k, lmax in enumerate([31, 63]):
+        g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
+        plans.append(sht.Plan(sht.Geometry.from_inputs(g), lmax, spin=0, ntrans=1 + k))
+        alms.append(to_dev(si.random_alm(lmax, lmax, 1 + k, 0, tag=30 + k)))
+    b = sht.Batch(plans)
+    maps = b.alm2map(alms)
+    back = b.map2alm(maps)
+    for p, a, mp, ab in zip(plans, alms, maps, back):
+        assert np.array_equal(to_host(mp), to_host(p.alm2map(a)))
+        assert np.array_equal(to_host(ab), to_host(p.map2alm(mp)))
+
+
+def test_valu_unsupported_combinations_rejected():
+    sht = _sht()
+    g = sht.Geometry.from_inputs(si.gauss_geometry(16, 31))
+    for kw in (dict(spin=2), dict(spin=0, precision="fp32_mfma")):
+        p = sht.Plan(g, 15, ntrans=1, **kw)
+        assert p.tuning()["valu"] == 0
+        with pytest.raises(sht.ShtError) as e:
+            p.set_tuning(valu=1)
+        assert e.value.status == sht.SHT_EUNSUPPORTED
