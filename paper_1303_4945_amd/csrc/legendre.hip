@@ -35,6 +35,8 @@
 // fixed order (deterministic, no atomics).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sht_internal.h"
 
 namespace sht {
@@ -964,190 +966,353 @@ __global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_ana
 //
 // For a few simultaneous spin-0 transforms most matrix-core columns would be
 // empty (2 of 16 for one transform), so the products run on the vector units
-// instead, with no empty columns: every FMA is one of the algorithm's
-// (Sect. 3.2's loop nests, one ring slot per lane).
-//   synthesis: lane = slot; per degree the recursion's two FMAs and, per
-//     transform, two FMAs with c f_l a_lm broadcast from LDS into the slot's
-//     even and odd class accumulators (no reduction at all);
-//   analysis: the recursion (lane = slot) writes a chunk of mu_l to LDS; the
-//     products then run transposed, lane = degree (and half of the slots):
-//     every lane sums its degree over the slots of the tile against the
-//     stationary phases G_t +- G_(pi-t) broadcast from LDS, so no cross-lane
-//     reduction per degree is needed; the two slot halves are added once per
-//     chunk, and the wavefronts' partial sums in a fixed order (deterministic).
+// instead, with no empty columns: every FMA is one of the algorithm's (the
+// loop nests of Sect. 3.2, several ring slots per lane).  A lane runs the
+// recursion chains of K slots (slots lane + 64 k of its tile group), so that
+// each wave-uniform step coefficient serves K chains.  The coefficients of a
+// chunk of degrees are loaded with vector loads one chunk ahead, staged in
+// LDS and read back as broadcasts.
+//   synthesis: per degree, per slot the recursion's two FMAs and per transform
+//     two FMAs with f_l a_lm into the slot's even and odd class accumulators;
+//     no reduction at all;
+//   analysis: per degree, per slot two FMAs per transform with the stationary
+//     phases G_t +- G_(pi-t) of the slot, summed over the lane's K slots in
+//     registers; every few degrees the 64 lanes' partial sums (8 values) are
+//     reduced by a butterfly whose first steps halve the values a lane holds
+//     (permlane32/16 swaps, a DPP mirror) and whose last steps add DPP copies;
+//     the wavefronts' sums are added in LDS in a fixed order (deterministic).
 
-// One recursion chunk of LC degrees (chains of a wave as in chain_chunk),
-// calling emit(t, value) for each degree offset t with value = mu_l (0 outside
-// [l0, lmax] and while the lane's scale k < 0).
-template <int LC, typename Emit>
-__device__ __forceinline__ void chain_chunk_emit(Chain &c, const double4 *__restrict__ cf, bool diff, bool &slow,
-                                                 int l0, int lc, int lmax, double thr, double down, Emit emit)
+// One step of a spin-0 chain with the staged coefficients q = (alpha, beta,
+// alpha + beta - 2, -) of the degree.
+template <bool DIFF>
+__device__ __forceinline__ void chain_step(Chain &c, const double4 q)
 {
+    if (DIFF) {
+        const double eps = fma(q.x, c.ms2, q.z);
+        c.aux = fma(eps, c.mu, c.aux);
+        c.mu += c.aux;
+    } else {
+        const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
+        c.aux = c.mu;
+        c.mu = nx;
+    }
+}
+
+// One chunk of LC degrees lc .. lc+LC-1 of the K chains of every lane, in
+// groups of G degrees: emit(u, k, mu, d) for each degree offset t = g + u and
+// chain k, with mu = mu_l (0 outside [l0, lmax] and while the chain's scale
+// k < 0) and d = load(t) (the staged wave-uniform data of the degree: step
+// coefficients in .q), then gend(g) at the end of the group.  Only the G
+// degrees of a group are unrolled, so the caller's registers are indexed by u
+// alone and the compiler cannot keep the mu of the whole chunk alive.
+template <int LC, int G, int K, bool DIFF, typename Load, typename Emit, typename GroupEnd>
+__device__ __forceinline__ void chains_chunk(Chain (&c)[K], bool &slow, int l0, int lc, int lmax, double thr,
+                                             double down, Load load, Emit emit, GroupEnd gend)
+{
+    static_assert(LC % G == 0, "whole groups");
     if (!slow && lc >= l0 && lc + LC <= lmax) {
-        if (diff) {
-#pragma unroll 4
-            for (int t = 0; t < LC; ++t) {
-                const double4 q = cf[t];
-                emit(t, c.mu);
-                const double eps = fma(q.x, c.ms2, q.z);
-                c.aux = fma(eps, c.mu, c.aux);
-                c.mu += c.aux;
+        // every degree steps and every chain is at scale 0: no masks
+#pragma unroll 1
+        for (int g = 0; g < LC; g += G) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const auto d = load(g + u);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    emit(u, k, c[k].mu, d);
+                    chain_step<DIFF>(c[k], d.q);
+                }
             }
-        } else {
-#pragma unroll 4
-            for (int t = 0; t < LC; ++t) {
-                const double4 q = cf[t];
-                emit(t, c.mu);
-                const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
-                c.aux = c.mu;
-                c.mu = nx;
-            }
+            gend(g);
         }
         return;
     }
-#pragma unroll 4
-    for (int t = 0; t < LC; ++t) {
-        const int l = lc + t;
-        emit(t, (l >= l0 && l <= lmax && c.k == 0) ? c.mu : 0.0);
-        if (l >= l0 && l < lmax) {
-            const double4 q = cf[t];
-            if (diff) {
-                const double eps = fma(q.x, c.ms2, q.z);
-                c.aux = fma(eps, c.mu, c.aux);
-                c.mu += c.aux;
-            } else {
-                const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
-                c.aux = c.mu;
-                c.mu = nx;
+    // Masked form: a chain contributes only at scale 0; its scale is checked
+    // once per group (between two checks |mu| grows by less than 3^G, far
+    // below the headroom above the threshold), so a chain that crosses the
+    // threshold inside a group enters at the next group -- the terms left out
+    // are below 2^-(S/2) 3^G relative and do not show in double precision.
+#pragma unroll 1
+    for (int g = 0; g < LC; g += G) {
+        double on[K];   // 1 at scale 0, else 0
+#pragma unroll
+        for (int k = 0; k < K; ++k) on[k] = c[k].k == 0 ? 1.0 : 0.0;
+        if (lc + g >= l0 && lc + g + G <= lmax) {
+            // the group lies inside [l0, lmax): every degree counts and steps
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const auto d = load(g + u);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    emit(u, k, c[k].mu * on[k], d);
+                    chain_step<DIFF>(c[k], d.q);
+                }
             }
-            if (c.k < 0 && fabs(c.mu) >= thr) {
-                c.mu *= down;
-                c.aux *= down;
-                c.k += 1;
+        } else {
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int l = lc + g + u;
+                const bool in = l >= l0 && l <= lmax, steps = l >= l0 && l < lmax;
+                const auto d = load(g + u);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    emit(u, k, in ? c[k].mu * on[k] : 0.0, d);
+                    if (steps) chain_step<DIFF>(c[k], d.q);
+                }
             }
         }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool up = c[k].k < 0 && fabs(c[k].mu) >= thr;
+            c[k].mu = up ? c[k].mu * down : c[k].mu;
+            c[k].aux = up ? c[k].aux * down : c[k].aux;
+            c[k].k += up ? 1 : 0;
+        }
+        gend(g);
     }
-    slow = wave_any(c.k < 0);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) any = any || c[k].k < 0;
+    slow = wave_any(any);
 }
 
+// chains of the K slots of this lane (tile[k] < 0: none), the form (difference
+// form if any slot of the wave is close to a pole) and the scale flag
+template <int K>
+__device__ __forceinline__ void chains_init(const LegView &v, int m, const int (&tile)[K], int lane, Chain (&c)[K],
+                                            bool &diff, bool &slow)
+{
+    bool d = false, s = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        c[k] = chain_init(v, m, tile[k] >= 0 ? tile[k] * 64 + lane : v.nslots, 0);
+        d = d || c[k].x > DIFF_FORM_COS;
+        s = s || c[k].k < 0;
+    }
+    diff = wave_any(d);
+    slow = wave_any(s);
+    if (diff)
+#pragma unroll
+        for (int k = 0; k < K; ++k) c[k].aux = c[k].mu;
+}
+
+constexpr int VSYN_LC = 16;   // degrees per chunk of the vector synthesis
+
+// staged data of one degree of the vector synthesis
 template <int J>
-struct SynValuShared {
-    double4 cfs[2][SYN_LC];          // step coefficients of two chunks
-    double2 co[2][SYN_LC][J];        // c f_l a_lm of the chunk's degrees, per transform
+struct SynStage {
+    double4 q;        // alpha, beta, alpha + beta - 2, 0
+    double2 co[J];    // f_l a_lm per transform (zero beyond lmax and for absent transforms)
 };
 
-// Work item (m, 64-slot tile, J transforms from t0), one wavefront.
-template <int J>
+// Work item (m, tile group of K tiles from it.tile, J transforms from t0), one wavefront.
+template <int J, int K>
 __global__ __launch_bounds__(64) void k_legendre_synth_valu(LegView v, const WaveItem *__restrict__ items,
                                                             const double *__restrict__ alm,
                                                             double *__restrict__ phase)
 {
-    constexpr int LC = SYN_LC;
-    __shared__ SynValuShared<J> sh;
+    constexpr int LC = VSYN_LC;
+    __shared__ SynStage<J> st[2][LC];
     const WaveItem it = items[blockIdx.x];
     if (it.m < 0) return;
     const int lane = threadIdx.x;
-    const int m = it.m, tile = it.tile, t0 = it.t0, lmax = v.lmax;
-    const int l0 = m;   // spin 0: l0 + m even, the first chunk starts at l0
+    const int m = it.m, t0 = it.t0, lmax = v.lmax;
+    const int l0 = m;   // spin 0: l0 + m even, chunks start at l0 (class of offset t = t & 1)
     const double4 *coef = v.coef + v.coef_ofs[m];
     const double *flm = v.fl + v.coef_ofs[m];
     const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
     const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
-    Chain cs = chain_init(v, m, tile * 64 + lane, 0);
-    const bool diff = wave_any(cs.x > DIFF_FORM_COS);
-    if (diff) cs.aux = cs.mu;
-    bool slow = wave_any(cs.k < 0);
+    int tile[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) tile[k] = it.tile + k < v.ntiles ? it.tile + k : -1;
+    Chain cs[K];
+    bool diff, slow;
+    chains_init<K>(v, m, tile, lane, cs, diff, slow);
 
-    // the chunk's step coefficients and c f_l a_lm (zero outside [l0, lmax], for
-    // absent transforms and for Im at m = 0: ignored entries never reach the sums)
+    // lane t < LC fetches degree lc + t of a chunk (clamped addresses; masked
+    // when staged)
+    double4 nq;
+    double nf;
+    double2 na[J];
+    auto fetch = [&](int lc) {
+        const int l = lc + (lane % LC);
+        const int lcl = l > lmax ? lmax : l;
+        nq = coef[lcl];
+        nf = flm[lcl];
+#pragma unroll
+        for (int tr = 0; tr < J; ++tr) {
+            const double2 *ar = reinterpret_cast<const double2 *>(alm) +
+                                (int64_t)(t0 + tr < v.ntrans ? t0 + tr : 0) * v.nalm + mbase;
+            na[tr] = ar[lcl];
+        }
+    };
     auto stage = [&](int buf, int lc) {
         if (lane < LC) {
             const int l = lc + lane;
-            const double4 c = (l >= l0 && l < lmax) ? coef[l] : double4{0, 0, 0, 0};
-            sh.cfs[buf][lane] = chain_coef(c, false, 0.0);
-        }
-        for (int e = lane; e < LC * J; e += 64) {
-            const int t = e / J, tr = e % J;
-            const int l = lc + t;
-            double2 a = make_double2(0.0, 0.0);
-            if (l <= lmax && t0 + tr < v.ntrans) {
-                const double f = flm[l];
-                const double *ap = alm + ((int64_t)(t0 + tr) * v.nalm + mbase + l) * 2;
-                a = make_double2(ap[0] * f, m == 0 ? 0.0 : ap[1] * f);
-            }
-            sh.co[buf][t][tr] = a;
+            SynStage<J> e;
+            e.q = (l < lmax) ? double4{nq.x, nq.y, nq.z, 0.0} : double4{0, 0, 0, 0};
+            const double f = l <= lmax ? nf : 0.0;
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr)
+                e.co[tr] = (t0 + tr < v.ntrans) ? make_double2(na[tr].x * f, m == 0 ? 0.0 : na[tr].y * f)
+                                                : make_double2(0.0, 0.0);
+            st[buf][lane] = e;
         }
     };
 
-    double2 acc[2][J];
+    double2 acc[2][K][J];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int tr = 0; tr < J; ++tr) acc[p][tr] = make_double2(0.0, 0.0);
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) acc[p][k][tr] = make_double2(0.0, 0.0);
+    fetch(l0);
     stage(0, l0);
     wave_sync();
-    int chunk = 0;
-    for (int lc = l0; lc <= lmax; lc += LC, ++chunk) {
-        const int buf = chunk & 1;
-        if (lc + LC <= lmax) stage(buf ^ 1, lc + LC);
-        chain_chunk_emit<LC>(cs, sh.cfs[buf], diff, slow, l0, lc, lmax, thr, down, [&](int t, double mu) {
+    auto run = [&](auto form) {
+        constexpr bool DIFF = decltype(form)::value;
+        int chunk = 0;
+        for (int lc = l0; lc <= lmax; lc += LC, ++chunk) {
+            const int buf = chunk & 1;
+            const bool more = lc + LC <= lmax;
+            if (more) fetch(lc + LC);
+            chains_chunk<LC, 4, K, DIFF>(
+                cs, slow, l0, lc, lmax, thr, down, [&](int t) -> const SynStage<J> & { return st[buf][t]; },
+                [&](int u, int k, double mu, const SynStage<J> &d) {
 #pragma unroll
-            for (int tr = 0; tr < J; ++tr) {
-                const double2 a = sh.co[buf][t][tr];
-                acc[t & 1][tr].x = fma(mu, a.x, acc[t & 1][tr].x);
-                acc[t & 1][tr].y = fma(mu, a.y, acc[t & 1][tr].y);
-            }
-        });
-        wave_sync();
-    }
+                    for (int tr = 0; tr < J; ++tr) {   // class of the degree: u & 1 (groups of four)
+                        acc[u & 1][k][tr].x = fma(mu, d.co[tr].x, acc[u & 1][k][tr].x);
+                        acc[u & 1][k][tr].y = fma(mu, d.co[tr].y, acc[u & 1][k][tr].y);
+                    }
+                },
+                [](int) {});
+            wave_sync();   // this chunk's reads of the other buffer are issued
+            if (more) stage(buf ^ 1, lc + LC);
+            wave_sync();
+        }
+    };
+    if (diff) run(std::true_type{});
+    else run(std::false_type{});
+
     // ring t = A0 + A1, ring pi - t = A0 - A1
-    const int slot = tile * 64 + lane;
-    if (slot >= v.nslots) return;
-    const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
     double2 *ph = reinterpret_cast<double2 *>(phase);
 #pragma unroll
-    for (int tr = 0; tr < J; ++tr) {
-        const int t = t0 + tr;
-        if (t >= v.ntrans) break;
-        const int64_t rowbase = (int64_t)t * v.nrings;
-        const double2 a0 = acc[0][tr], a1 = acc[1][tr];
-        if (yn >= 0) ph[(rowbase + yn) * (v.mmax + 1) + m] = make_double2(a0.x + a1.x, a0.y + a1.y);
-        if (ys >= 0) ph[(rowbase + ys) * (v.mmax + 1) + m] = make_double2(a0.x - a1.x, a0.y - a1.y);
+    for (int k = 0; k < K; ++k) {
+        if (tile[k] < 0) continue;
+        const int slot = tile[k] * 64 + lane;
+        if (slot >= v.nslots) continue;
+        const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
+#pragma unroll
+        for (int tr = 0; tr < J; ++tr) {
+            const int t = t0 + tr;
+            if (t >= v.ntrans) break;
+            const int64_t rowbase = (int64_t)t * v.nrings;
+            const double2 a0 = acc[0][k][tr], a1 = acc[1][k][tr];
+            if (yn >= 0) ph[(rowbase + yn) * (v.mmax + 1) + m] = make_double2(a0.x + a1.x, a0.y + a1.y);
+            if (ys >= 0) ph[(rowbase + ys) * (v.mmax + 1) + m] = make_double2(a0.x - a1.x, a0.y - a1.y);
+        }
     }
 }
 
-// wavefronts per analysis work group (vector path; eight for one transform,
-// one work group per CU, measured slower)
-template <int J>
-constexpr int anv_nw() { return 4; }
-constexpr int ANV_LC = 32;   // degrees per chunk
-constexpr int ANV_ROW = 65;  // LDS row of mu: 64 slots (+ pad)
+// ---- butterfly reduction of 32 values over the 64 lanes of a wavefront
 
-template <int J>
-struct AnaValuShared {
-    static constexpr int NW = anv_nw<J>();
-    double lam[NW][ANV_LC][ANV_ROW];       // mu of the wavefront's tile, [degree][slot]
-    double2 g[NW][2][64][J];               // its stationary phases: class, slot, transform
-    double2 part[NW][ANV_LC][J];           // its partial sums of the chunk
-    double4 cfs[2][ANV_LC];                // step coefficients, staged one chunk ahead
-    double fls[2][ANV_LC];                 // f_l of the chunk's degrees
-};
+__device__ __forceinline__ double dpp_f64(double x, int ctrl)
+{
+    const long long b = __double_as_longlong(x);
+    int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    switch (ctrl) {   // the control must be a constant of the builtin
+    case 0x140:
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false);
+        break;
+    case 0x141:
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
+        break;
+    case 0x4E:
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+        break;
+    default:
+        lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+        break;
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lanes L < 32 get a_L + a_(L+32), lanes L >= 32 get b_(L-32) + b_L.
+__device__ __forceinline__ double swap32_add(double a, double b)
+{
+    const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)(ia & 0xffffffffLL), (unsigned)(ib & 0xffffffffLL),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+    const double r0 = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    const double r1 = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+    return r0 + r1;
+}
+
+// The same within each half of 32 lanes: bit 4 of the lane clear: a_L + a_(L+16),
+// set: b_(L-16) + b_L.
+__device__ __forceinline__ double swap16_add(double a, double b)
+{
+    const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)(ia & 0xffffffffLL), (unsigned)(ib & 0xffffffffLL),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+    const double r0 = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    const double r1 = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+    return r0 + r1;
+}
+
+// One halving step with a DPP partner that differs from the lane in bit `bit`
+// (and possibly lower bits): the lane keeps a (bit clear) or b (bit set) and
+// adds the partner's copy of the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_half_add(double a, double b, bool upper)
+{
+    const double keep = upper ? b : a, send = upper ? a : b;
+    return keep + dpp_f64(send, CTRL);
+}
+
+// x[0..7] of every lane -> every lane L holds the sum over all 64 lanes of
+// x[L >> 3] (halving steps over lane bits 5, 4 and 3, then plain sums over the
+// lanes that differ in bits 0-2).
+__device__ __forceinline__ double wave_reduce8(double (&x)[8], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = swap32_add(x[i], x[i + 4]);   // index i + 4 b5
+#pragma unroll
+    for (int i = 0; i < 2; ++i) x[i] = swap16_add(x[i], x[i + 2]);   // + 2 b4
+    double r = dpp_half_add<0x140>(x[0], x[1], lane & 8);            // row mirror: + b3
+    r += dpp_f64(r, 0x141);                                           // lanes L ^ 7
+    r += dpp_f64(r, 0x4E);                                            // L ^ 2
+    return r + dpp_f64(r, 0xB1);                                      // L ^ 1
+}
+
+constexpr int ANV_NW = 4;   // wavefronts per analysis work group (vector path)
 
 // Work group = one m and J transforms from blockIdx.y J; the m's active tiles
-// are taken anv_nw at a time (one per wavefront), and every pass reads and
-// writes the m's a_lm row once.
-template <int J>
-__global__ __launch_bounds__(64 * anv_nw<J>()) void k_legendre_anal_valu(LegView v, const int *__restrict__ mlist,
-                                                                    const double *__restrict__ phase,
-                                                                    double *__restrict__ alm, int mode)
+// are dealt K per wavefront, NW K per pass, and every pass after the first
+// adds into the m's a_lm row.
+template <int J, int K>
+__global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, const int *__restrict__ mlist,
+                                                                   const double *__restrict__ phase,
+                                                                   double *__restrict__ alm, int mode)
 {
-    constexpr int LC = ANV_LC, NW = anv_nw<J>(), NT = 64 * NW;
-    __shared__ AnaValuShared<J> sh;
+    constexpr int LC = 16 / J;           // degrees per chunk: 32 output values per wavefront
+    constexpr int NV = LC * J * 2;
+    constexpr int GD = 4 / J;            // degrees per reduction group: 8 values
+    static_assert(NV == 32 && GD * J * 2 == 8, "value layout");
+    __shared__ double part[2][ANV_NW][NV];
+    __shared__ double4 stq[2][LC];
     const int m = mlist[blockIdx.x];
     const int t0 = (int)blockIdx.y * J;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lmax = v.lmax;
-    const int l0 = m;
+    const int nw = (int)(blockDim.x >> 6);
+    const int lmax = v.lmax, l0 = m;
     const double4 *coef = v.coef + v.coef_ofs[m];
     const double *flm = v.fl + v.coef_ofs[m];
     const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
@@ -1155,40 +1320,43 @@ __global__ __launch_bounds__(64 * anv_nw<J>()) void k_legendre_anal_valu(LegView
     const bool grad = mode & ANA_MODE_GRAD;
     const double2 *G = reinterpret_cast<const double2 *>(phase);
     double2 *out = reinterpret_cast<double2 *>(alm);
+    // output element of this thread (tid < NV): value index = (t J + tr) 2 + re/im
+    const int o_t = (tid >> 1) / J, o_tr = (tid >> 1) % J, o_im = tid & 1;
+    const bool o_thread = tid < NV && t0 + o_tr < v.ntrans;
+    double *const orow = o_thread ? reinterpret_cast<double *>(out + (int64_t)(t0 + o_tr) * v.nalm + mbase) + o_im
+                                  : nullptr;
+    const double fac = (grad && m > 0) ? 2.0 : 1.0;   // fac_m of the real-field gradient
 
-    auto stage = [&](int buf, int lc) {   // wavefront 0
-        if (lane < LC) {
-            const int l = lc + lane;
-            const int lcl = l > lmax ? lmax : l;
-            const double4 c = (l < lmax) ? coef[lcl] : double4{0, 0, 0, 0};
-            sh.cfs[buf][lane] = chain_coef(c, false, 0.0);
-            sh.fls[buf][lane] = (l <= lmax) ? flm[lcl] : 0.0;
-        }
-    };
     int ntiles_act = 0;
     for (int t = 0; t < v.ntiles; ++t) ntiles_act += v.tile_mlim[t] >= m;
-    int tscan = 0, tcount = 0;
+    int tscan = 0, tcount = 0, cidx = 0;
     bool first = true;
     while (tcount < ntiles_act || first) {
-        // this pass's tile of this wavefront (-1: none)
-        int ptile = -1;
+        // this pass's tiles of this wavefront (the m's active tiles in order, K each)
+        int tile[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) tile[k] = -1;
         {
-            int k = 0;
-            for (; tscan < v.ntiles && k < NW; ++tscan) {
+            int n = 0;
+            for (; tscan < v.ntiles && n < nw * K; ++tscan) {
                 if (v.tile_mlim[tscan] < m) continue;
-                if (k == wave) ptile = tscan;
-                ++k;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (n == wave * K + k) tile[k] = tscan;
+                ++n;
             }
-            tcount += k;
+            tcount += n;
         }
-        // stationary phases G_t +- G_(pi-t) of the tile's slots (zero for
-        // missing rings, absent transforms and when the wavefront has no tile)
-        Chain cs = chain_init(v, m, ptile >= 0 ? ptile * 64 + lane : v.nslots, 0);
-        const bool diff = wave_any(cs.x > DIFF_FORM_COS);
-        if (diff) cs.aux = cs.mu;
-        bool slow = wave_any(cs.k < 0);
-        {
-            const int slot = ptile >= 0 ? ptile * 64 + lane : v.nslots;
+        const bool active = tile[0] >= 0;   // tiles are dealt to k = 0 first
+        Chain cs[K];
+        bool diff, slow;
+        chains_init<K>(v, m, tile, lane, cs, diff, slow);
+        // stationary phases G_t +- G_(pi-t) of the lane's slots (zero for missing
+        // rings and slots, absent transforms)
+        double2 g[K][2][J];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int slot = tile[k] >= 0 ? tile[k] * 64 + lane : v.nslots;
             const bool ok = slot < v.nslots;
             const int yn = ok ? v.slot_yn[slot] : -1, ys = ok ? v.slot_ys[slot] : -1;
 #pragma unroll
@@ -1199,87 +1367,88 @@ __global__ __launch_bounds__(64 * anv_nw<J>()) void k_legendre_anal_valu(LegView
                 const double2 gs0 = G[(rowbase + (ys >= 0 ? ys : 0)) * (v.mmax + 1) + m];
                 const double2 gn = (tok && yn >= 0) ? gn0 : make_double2(0.0, 0.0);
                 const double2 gs = (tok && ys >= 0) ? gs0 : make_double2(0.0, 0.0);
-                sh.g[wave][0][lane][tr] = make_double2(gn.x + gs.x, gn.y + gs.y);
-                sh.g[wave][1][lane][tr] = make_double2(gn.x - gs.x, gn.y - gs.y);
+                g[k][0][tr] = make_double2(gn.x + gs.x, gn.y + gs.y);
+                g[k][1][tr] = make_double2(gn.x - gs.x, gn.y - gs.y);
             }
         }
-        if (wave == 0) stage(0, l0);
+        // staged step coefficients (alpha, beta, alpha + beta - 2, f_l) of a
+        // chunk, shared by the wavefronts: thread t < LC of wavefront 0 fetches
+        // degree lc + t one chunk ahead and stages it after its own products
+        double4 nq = double4{0, 0, 0, 0};
+        double nf = 0.0;
+        auto fetch = [&](int lc) {
+            if (wave == 0) {
+                const int l = lc + (lane % LC);
+                const int lcl = l > lmax ? lmax : l;
+                nq = coef[lcl];
+                nf = flm[lcl];
+            }
+        };
+        auto stage = [&](int buf, int lc) {
+            if (wave == 0 && lane < LC) {
+                const int l = lc + lane;
+                stq[buf][lane] = l < lmax ? double4{nq.x, nq.y, nq.z, nf} : double4{0, 0, 0, l <= lmax ? nf : 0.0};
+            }
+        };
+        fetch(l0);
+        stage(cidx & 1, l0);
         __syncthreads();
-        int chunk = 0;
-        for (int lc = l0; lc <= lmax; lc += LC, ++chunk) {
-            const int buf = chunk & 1;
-            // the previous passes' sums of this thread's output element (if it
-            // has one), loaded now so that the load is in flight during the
-            // recursion and the products
-            double2 prev = make_double2(0.0, 0.0);
-            if (!first && tid < LC * J) {
-                const int td = tid / J, tr = tid % J;
-                const int l = lc + td;
-                if (l <= lmax && t0 + tr < v.ntrans) prev = out[(int64_t)(t0 + tr) * v.nalm + mbase + l];
-            }
-            // the recursion of the tile, mu to LDS (lane = slot)
-            double *lw = &sh.lam[wave][0][0];
-            if (ptile >= 0)
-                chain_chunk_emit<LC>(cs, sh.cfs[buf], diff, slow, l0, lc, lmax, thr, down,
-                                     [&](int t, double mu) { lw[t * ANV_ROW + lane] = mu; });
-            wave_sync();
-            // products, lane = degree t and slot part h (64 / LC parts of LC slots)
-            constexpr int PS = LC;   // slots per part
-            const int t = lane & (LC - 1), h = lane / LC;
-            double2 sacc[J];
+        for (int lc = l0; lc <= lmax; lc += LC, ++cidx) {
+            const int buf = cidx & 1;
+            const bool more = lc + LC <= lmax;
+            if (more) fetch(lc + LC);
+            // the earlier passes' sum of this thread's output element, in flight
+            // during the chunk's arithmetic
+            const int ol = lc + o_t;
+            double prev = 0.0;
+            if (!first && o_thread && ol <= lmax) prev = orow[2 * (int64_t)ol];
+            // value index within a group: (u J + tr) 2 + re/im; over the chunk:
+            // that + 8 (group offset / GD), i.e. (t J + tr) 2 + re/im
+            double x[8];
 #pragma unroll
-            for (int tr = 0; tr < J; ++tr) sacc[tr] = make_double2(0.0, 0.0);
-            if (ptile >= 0) {
-                const int cls = t & 1;
-                const double *row = lw + t * ANV_ROW + h * PS;
-#pragma unroll 8
-                for (int k = 0; k < PS; ++k) {
-                    const double lv = row[k];
+            for (int i = 0; i < 8; ++i) x[i] = 0.0;
+            struct AnaD {
+                double4 q;
+            };
+            auto load = [&](int t) { return AnaD{stq[buf][t]}; };
+            auto emit = [&](int u, int k, double mu, const AnaD &) {
 #pragma unroll
-                    for (int tr = 0; tr < J; ++tr) {
-                        const double2 gv = sh.g[wave][cls][h * PS + k][tr];
-                        sacc[tr].x = fma(lv, gv.x, sacc[tr].x);
-                        sacc[tr].y = fma(lv, gv.y, sacc[tr].y);
-                    }
+                for (int tr = 0; tr < J; ++tr) {
+                    const double2 gv = g[k][u & 1][tr];   // GD even: class of the degree = u & 1
+                    x[(u * J + tr) * 2] = fma(mu, gv.x, x[(u * J + tr) * 2]);
+                    x[(u * J + tr) * 2 + 1] = fma(mu, gv.y, x[(u * J + tr) * 2 + 1]);
                 }
-            }
+            };
+            auto gend = [&](int g0) {
+                const double r = wave_reduce8(x, lane);
+                if ((lane & 7) == 0) part[buf][wave][(g0 / GD) * 8 + (lane >> 3)] = r;
 #pragma unroll
-            for (int tr = 0; tr < J; ++tr) {
-#pragma unroll
-                for (int off = LC; off < 64; off *= 2) {
-                    sacc[tr].x += __shfl_xor(sacc[tr].x, off);
-                    sacc[tr].y += __shfl_xor(sacc[tr].y, off);
-                }
-                if (lane < LC) sh.part[wave][lane][tr] = sacc[tr];
+                for (int i = 0; i < 8; ++i) x[i] = 0.0;
+            };
+            if (active) {
+                if (diff) chains_chunk<LC, GD, K, true>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
+                else chains_chunk<LC, GD, K, false>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
+            } else if (lane < NV) {
+                part[buf][wave][lane] = 0.0;
             }
-            if (wave == 0 && lc + LC <= lmax) stage(buf ^ 1, lc + LC);
+            if (more) stage(buf ^ 1, lc + LC);
             __syncthreads();
-            // the wavefronts' sums in a fixed order, times f_l (and fac_m), into a_lm
-            static_assert(LC * J <= NT, "one output element per thread");
-            if (tid < LC * J) {
-                const int td = tid / J, tr = tid % J;
-                const int l = lc + td;
-                if (l <= lmax && t0 + tr < v.ntrans) {
-                    double2 sum = sh.part[0][td][tr];
-#pragma unroll
-                    for (int w = 1; w < NW; ++w) {
-                        sum.x += sh.part[w][td][tr].x;
-                        sum.y += sh.part[w][td][tr].y;
-                    }
-                    double f = sh.fls[buf][td];
-                    if (grad && m > 0) f *= 2.0;   // fac_m of the real-field gradient
-                    sum = make_double2(sum.x * f, m == 0 ? 0.0 : sum.y * f);
-                    if (!first) sum = make_double2(prev.x + sum.x, prev.y + sum.y);
-                    out[(int64_t)(t0 + tr) * v.nalm + mbase + l] = sum;
-                }
+            if (o_thread && ol <= lmax) {
+                double sum = part[buf][0][tid];
+                for (int w = 1; w < nw; ++w) sum += part[buf][w][tid];
+                double val = sum * stq[buf][o_t].w * fac;
+                if (m == 0 && o_im) val = 0.0;
+                orow[2 * (int64_t)ol] = first ? val : prev + val;
             }
-            __syncthreads();
+            // part[buf] and stq[buf] are written again in the next chunk but one,
+            // after the next barrier
         }
         first = false;
     }
 }
 
 __global__ void k_reset_counter(unsigned *counter)
+
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
@@ -1357,16 +1526,60 @@ static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, 
 
 int valu_jpg(const Plan &p) { return p.ntrans >= 2 ? 2 : 1; }
 
+// slot tiles per lane group of the vector kernels (K slots per lane): four
+// for one transform and two for two (the registers of three waves per SIMD)
+// where the plan has tiles enough to keep the waves busy, fewer for small grids
+int valu_k(const Plan &p)
+{
+    const int kmax = valu_jpg(p) == 1 ? 4 : 2;
+    const int k = p.ntiles >= 8 ? 4 : (p.ntiles >= 2 ? 2 : 1);
+    return k < kmax ? k : kmax;
+}
+
+template <int J, int K>
+static void launch_synth_valu_t(const Plan &p, const LegView &v, const double *alm, double *phase, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_legendre_synth_valu<J, K>), dim3((unsigned)p.synth_items.size()), dim3(64), 0, s, v,
+                       p.d_synth_items, alm, phase);
+}
+
+template <int J, int K>
+static void launch_anal_valu_t(const Plan &p, const LegView &v, const double *phase, double *alm, int mode,
+                               hipStream_t s)
+{
+    const int groups = (p.ntiles + K - 1) / K;
+    const int nw = groups < ANV_NW ? (groups > 0 ? groups : 1) : ANV_NW;
+    const dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + J - 1) / J));
+    hipLaunchKernelGGL((k_legendre_anal_valu<J, K>), grid, dim3(64 * nw), 0, s, v, p.d_anal_ms, phase, alm, mode);
+}
+
+template <int J>
+static void synth_valu_k(const Plan &p, const LegView &v, const double *alm, double *phase, hipStream_t s)
+{
+    switch (valu_k(p)) {
+    case 4: launch_synth_valu_t<J, (J == 1 ? 4 : 2)>(p, v, alm, phase, s); break;
+    case 2: launch_synth_valu_t<J, 2>(p, v, alm, phase, s); break;
+    default: launch_synth_valu_t<J, 1>(p, v, alm, phase, s); break;
+    }
+}
+
+template <int J>
+static void anal_valu_k(const Plan &p, const LegView &v, const double *phase, double *alm, int mode, hipStream_t s)
+{
+    switch (valu_k(p)) {
+    case 4: launch_anal_valu_t<J, (J == 1 ? 4 : 2)>(p, v, phase, alm, mode, s); break;
+    case 2: launch_anal_valu_t<J, 2>(p, v, phase, alm, mode, s); break;
+    default: launch_anal_valu_t<J, 1>(p, v, phase, alm, mode, s); break;
+    }
+}
+
 int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool deriv, hipStream_t s)
 {
     if (p.synth_items.empty()) return SHT_OK;
     const LegView v = make_leg_view(p);
     if (p.tune.valu) {
-        const dim3 grid((unsigned)p.synth_items.size());
-        if (valu_jpg(p) == 1)
-            hipLaunchKernelGGL(k_legendre_synth_valu<1>, grid, dim3(64), 0, s, v, p.d_synth_items, alm, phase);
-        else
-            hipLaunchKernelGGL(k_legendre_synth_valu<2>, grid, dim3(64), 0, s, v, p.d_synth_items, alm, phase);
+        if (valu_jpg(p) == 1) synth_valu_k<1>(p, v, alm, phase, s);
+        else synth_valu_k<2>(p, v, alm, phase, s);
         return check_hip(hipGetLastError(), "legendre synthesis launch");
     }
     const int d = deriv ? 1 : 0;
@@ -1383,14 +1596,8 @@ int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mo
 {
     const LegView v = make_leg_view(p);
     if (p.tune.valu) {
-        const int j = valu_jpg(p);
-        const dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + j - 1) / j));
-        if (j == 1)
-            hipLaunchKernelGGL(k_legendre_anal_valu<1>, grid, dim3(64 * anv_nw<1>()), 0, s, v, p.d_anal_ms, phase, alm,
-                               mode);
-        else
-            hipLaunchKernelGGL(k_legendre_anal_valu<2>, grid, dim3(64 * anv_nw<2>()), 0, s, v, p.d_anal_ms, phase, alm,
-                               mode);
+        if (valu_jpg(p) == 1) anal_valu_k<1>(p, v, phase, alm, mode, s);
+        else anal_valu_k<2>(p, v, phase, alm, mode, s);
         return check_hip(hipGetLastError(), "legendre analysis launch");
     }
     if (p.precision == SHT_FP32_MFMA) dispatch_anal<true>(p, v, phase, alm, mode, s);

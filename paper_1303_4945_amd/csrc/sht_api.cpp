@@ -133,11 +133,16 @@ int build_synth_items(Plan &p)
         double cost = 0.0;
         for (int m = mb; m < std::min(p.mmax + 1, mb + MB); ++m) {
             const double lrange = (double)(p.lmax + 1 - std::max(m, p.spin));
-            for (int t = 0; t < p.ntiles; ++t) {
-                if (p.tile_mlim[t] < m) continue;
+            // one item per active slot tile, or (vector path) per group of K
+            // consecutive tiles with an active one
+            const int tstep = p.tune.valu ? valu_k(p) : 1;
+            for (int t = 0; t < p.ntiles; t += tstep) {
+                bool act = false;
+                for (int u = t; u < std::min(p.ntiles, t + tstep); ++u) act = act || p.tile_mlim[u] >= m;
+                if (!act) continue;
                 for (int gI = 0; gI < ngroups; ++gI) {
                     blk.push_back(WaveItem{m, t, gI * jpg, 0});
-                    cost += lrange;
+                    cost += lrange * tstep;
                 }
             }
         }

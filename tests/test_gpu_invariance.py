@@ -63,6 +63,29 @@ def test_rescale_step_invariance():
     assert rel_err(got, ref) < 1e-9
 
 
+def test_rescale_step_invariance_vector_path():
+    """The vector-unit kernels (spin 0, one transform) check a chain's scale
+    once per group of four degrees, so a chain enters up to three degrees late:
+    the terms left out are below 2^-(S/2) 3^4 relative, rounding level from
+    S = 128 on and ~1e-8 at S = 64."""
+    sht = _sht()
+    lmax = 1023
+    g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
+    geom = sht.Geometry.from_inputs(g)
+    a = to_dev(si.random_alm(lmax, lmax, 1, 0, tag=44))
+    ref_p = sht.Plan(geom, lmax, spin=0, rescale_bits=256)
+    assert ref_p.tuning()["valu"] == 1
+    ref = to_host(ref_p.alm2map(a))
+    back_ref = to_host(ref_p.map2alm(to_dev(ref)))
+    for bits in (128, 400, 640):
+        p = sht.Plan(geom, lmax, spin=0, rescale_bits=bits)
+        assert rel_err(to_host(p.alm2map(a)), ref) < 1e-13, bits
+        assert rel_err(to_host(p.map2alm(to_dev(ref))), back_ref) < 1e-13, bits
+    p = sht.Plan(geom, lmax, spin=0, rescale_bits=64)
+    assert rel_err(to_host(p.alm2map(a)), ref) < 1e-7
+    assert rel_err(to_host(p.map2alm(to_dev(ref))), back_ref) < 1e-7
+
+
 def _sampled_synthesis_check(g, lmax, spin, a_host, maps_host, rings, trans):
     ref = oracle.synthesis(g, lmax, lmax, spin, np.ascontiguousarray(a_host[trans]), rings=rings)
     pix = np.concatenate([np.arange(g.ofs[y], g.ofs[y] + g.nphi[y]) for y in rings])
