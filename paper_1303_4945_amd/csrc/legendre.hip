@@ -1293,6 +1293,7 @@ __device__ __forceinline__ double wave_reduce8(double (&x)[8], int lane)
 }
 
 constexpr int ANV_NW = 4;   // wavefronts per analysis work group (vector path)
+constexpr int ANV_CH = 64;  // degrees x transforms per chunk of the vector analysis
 
 // Work group = one m and J transforms from blockIdx.y J; the m's active tiles
 // are dealt K per wavefront, NW K per pass, and every pass after the first
@@ -1302,10 +1303,11 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
                                                                    const double *__restrict__ phase,
                                                                    double *__restrict__ alm, int mode)
 {
-    constexpr int LC = 16 / J;           // degrees per chunk: 32 output values per wavefront
-    constexpr int NV = LC * J * 2;
+    constexpr int LC = ANV_CH / J;       // degrees per chunk (one barrier and output round each)
+    constexpr int NV = LC * J * 2;       // output values of a chunk
     constexpr int GD = 4 / J;            // degrees per reduction group: 8 values
-    static_assert(NV == 32 && GD * J * 2 == 8, "value layout");
+    static_assert(GD * J * 2 == 8 && LC % GD == 0 && LC <= 64, "value layout");
+    constexpr int OPT = (NV + 63) / 64;  // output values per thread (at least one wavefront)
     __shared__ double part[2][ANV_NW][NV];
     __shared__ double4 stq[2][LC];
     const int m = mlist[blockIdx.x];
@@ -1320,12 +1322,13 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
     const bool grad = mode & ANA_MODE_GRAD;
     const double2 *G = reinterpret_cast<const double2 *>(phase);
     double2 *out = reinterpret_cast<double2 *>(alm);
-    // output element of this thread (tid < NV): value index = (t J + tr) 2 + re/im
-    const int o_t = (tid >> 1) / J, o_tr = (tid >> 1) % J, o_im = tid & 1;
-    const bool o_thread = tid < NV && t0 + o_tr < v.ntrans;
-    double *const orow = o_thread ? reinterpret_cast<double *>(out + (int64_t)(t0 + o_tr) * v.nalm + mbase) + o_im
-                                  : nullptr;
+    // output elements e = tid + j blockDim of a chunk: value index e = (t J + tr) 2 + re/im
     const double fac = (grad && m > 0) ? 2.0 : 1.0;   // fac_m of the real-field gradient
+    auto orow = [&](int e) {   // element e of degree lc + t lives at orow(e)[2 (lc + t)]
+        const int tr = (e >> 1) % J;
+        return reinterpret_cast<double *>(out + (int64_t)(t0 + tr) * v.nalm + mbase) + (e & 1);
+    };
+    auto o_valid = [&](int e) { return e < NV && t0 + (e >> 1) % J < v.ntrans; };
 
     int ntiles_act = 0;
     for (int t = 0; t < v.ntiles; ++t) ntiles_act += v.tile_mlim[t] >= m;
@@ -1397,11 +1400,15 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
             const int buf = cidx & 1;
             const bool more = lc + LC <= lmax;
             if (more) fetch(lc + LC);
-            // the earlier passes' sum of this thread's output element, in flight
+            // the earlier passes' sums of this thread's output elements, in flight
             // during the chunk's arithmetic
-            const int ol = lc + o_t;
-            double prev = 0.0;
-            if (!first && o_thread && ol <= lmax) prev = orow[2 * (int64_t)ol];
+            double prev[OPT];
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) {
+                const int e = tid + j * (int)blockDim.x;
+                const int ol = lc + (e >> 1) / J;
+                prev[j] = (!first && o_valid(e) && ol <= lmax) ? orow(e)[2 * (int64_t)ol] : 0.0;
+            }
             // value index within a group: (u J + tr) 2 + re/im; over the chunk:
             // that + 8 (group offset / GD), i.e. (t J + tr) 2 + re/im
             double x[8];
@@ -1428,17 +1435,21 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
             if (active) {
                 if (diff) chains_chunk<LC, GD, K, true>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
                 else chains_chunk<LC, GD, K, false>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
-            } else if (lane < NV) {
-                part[buf][wave][lane] = 0.0;
+            } else {
+                for (int e = lane; e < NV; e += 64) part[buf][wave][e] = 0.0;
             }
             if (more) stage(buf ^ 1, lc + LC);
             __syncthreads();
-            if (o_thread && ol <= lmax) {
-                double sum = part[buf][0][tid];
-                for (int w = 1; w < nw; ++w) sum += part[buf][w][tid];
-                double val = sum * stq[buf][o_t].w * fac;
-                if (m == 0 && o_im) val = 0.0;
-                orow[2 * (int64_t)ol] = first ? val : prev + val;
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) {
+                const int e = tid + j * (int)blockDim.x;
+                const int t = (e >> 1) / J, ol = lc + t;
+                if (!o_valid(e) || ol > lmax) continue;
+                double sum = part[buf][0][e];
+                for (int w = 1; w < nw; ++w) sum += part[buf][w][e];
+                double val = sum * stq[buf][t].w * fac;
+                if (m == 0 && (e & 1)) val = 0.0;
+                orow(e)[2 * (int64_t)ol] = first ? val : prev[j] + val;
             }
             // part[buf] and stq[buf] are written again in the next chunk but one,
             // after the next barrier
@@ -1526,12 +1537,14 @@ static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, 
 
 int valu_jpg(const Plan &p) { return p.ntrans >= 2 ? 2 : 1; }
 
-// slot tiles per lane group of the vector kernels (K slots per lane): four
-// for one transform and two for two (the registers of three waves per SIMD)
-// where the plan has tiles enough to keep the waves busy, fewer for small grids
-int valu_k(const Plan &p)
+// slot tiles per lane group of the vector kernels (K slots per lane) where the
+// plan has tiles enough to keep the waves busy, fewer for small grids:
+// synthesis two, analysis four for one transform and two for two (measured at
+// HEALPix N_side 1024, lmax 2047: synthesis 1.07 ms with two, 1.16 with four;
+// analysis 1.43 ms with four, 1.49 with two)
+int valu_k(const Plan &p, bool anal)
 {
-    const int kmax = valu_jpg(p) == 1 ? 4 : 2;
+    const int kmax = (anal && valu_jpg(p) == 1) ? 4 : 2;
     const int k = p.ntiles >= 8 ? 4 : (p.ntiles >= 2 ? 2 : 1);
     return k < kmax ? k : kmax;
 }
@@ -1556,8 +1569,7 @@ static void launch_anal_valu_t(const Plan &p, const LegView &v, const double *ph
 template <int J>
 static void synth_valu_k(const Plan &p, const LegView &v, const double *alm, double *phase, hipStream_t s)
 {
-    switch (valu_k(p)) {
-    case 4: launch_synth_valu_t<J, (J == 1 ? 4 : 2)>(p, v, alm, phase, s); break;
+    switch (valu_k(p, false)) {
     case 2: launch_synth_valu_t<J, 2>(p, v, alm, phase, s); break;
     default: launch_synth_valu_t<J, 1>(p, v, alm, phase, s); break;
     }
@@ -1566,7 +1578,7 @@ static void synth_valu_k(const Plan &p, const LegView &v, const double *alm, dou
 template <int J>
 static void anal_valu_k(const Plan &p, const LegView &v, const double *phase, double *alm, int mode, hipStream_t s)
 {
-    switch (valu_k(p)) {
+    switch (valu_k(p, true)) {
     case 4: launch_anal_valu_t<J, (J == 1 ? 4 : 2)>(p, v, phase, alm, mode, s); break;
     case 2: launch_anal_valu_t<J, 2>(p, v, phase, alm, mode, s); break;
     default: launch_anal_valu_t<J, 1>(p, v, phase, alm, mode, s); break;

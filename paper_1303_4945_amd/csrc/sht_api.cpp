@@ -135,7 +135,7 @@ int build_synth_items(Plan &p)
             const double lrange = (double)(p.lmax + 1 - std::max(m, p.spin));
             // one item per active slot tile, or (vector path) per group of K
             // consecutive tiles with an active one
-            const int tstep = p.tune.valu ? valu_k(p) : 1;
+            const int tstep = p.tune.valu ? valu_k(p, false) : 1;
             for (int t = 0; t < p.ntiles; t += tstep) {
                 bool act = false;
                 for (int u = t; u < std::min(p.ntiles, t + tstep); ++u) act = act || p.tile_mlim[u] >= m;

@@ -172,7 +172,7 @@ int tuning_check(const Plan &p, const sht_tuning &t);
 int apply_tuning(Plan &p, const sht_tuning &t);
 int anal_tpw_built(int spin, int ncb);   // tiles per wavefront of the built analysis kernels
 int valu_jpg(const Plan &p);             // transforms per work item of the vector-unit kernels
-int valu_k(const Plan &p);               // slot tiles per lane group of the vector-unit kernels
+int valu_k(const Plan &p, bool anal);    // slot tiles per lane group of the vector-unit kernels
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s);
 
 // persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
