@@ -1560,8 +1560,12 @@ template <int J, int K>
 static void launch_anal_valu_t(const Plan &p, const LegView &v, const double *phase, double *alm, int mode,
                                hipStream_t s)
 {
+    // wavefronts per work group: two for one transform, four for two (measured
+    // at HEALPix N_side 1024, lmax 2047: one transform 1.39 ms with two, 1.47 with
+    // four, 1.56 with eight; two transforms 2.51 ms with four, 3.42 with two)
     const int groups = (p.ntiles + K - 1) / K;
-    const int nw = groups < ANV_NW ? (groups > 0 ? groups : 1) : ANV_NW;
+    const int nwmax = J == 1 ? 2 : ANV_NW;
+    const int nw = groups < nwmax ? (groups > 0 ? groups : 1) : nwmax;
     const dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + J - 1) / J));
     hipLaunchKernelGGL((k_legendre_anal_valu<J, K>), grid, dim3(64 * nw), 0, s, v, p.d_anal_ms, phase, alm, mode);
 }
