@@ -251,7 +251,8 @@ int sht_memory_stats(int64_t *live_buffers, int64_t *live_bytes);
    one direction per call) as one stream-ordered unit (Sect. 3.2's simultaneous
    transforms, with mixed band limits and grids): the Legendre analyses of
    every plan are merged into one persistent launch over a queue of items
-   popped by an atomic counter; the Legendre syntheses (each plan's die-aware
+   popped by an atomic counter (plans tuned to the vector path run their own
+   analysis launches instead); the Legendre syntheses (each plan's die-aware
    item list) and the ring FFTs run per plan, on concurrent streams; on a
    non-null stream the whole sequence is captured once into a HIP graph and
    replayed (captured again when the buffers, the stream or the tuning of a
@@ -284,8 +285,9 @@ enum { SHT_QUEUE_COST = 0, SHT_QUEUE_MPAIRS = 1 };
 int sht_batch_configure(sht_batch *b, int queue_order, int concurrent);
 
 /* Launch-shape parameters of a plan's Legendre kernels (Sect. 3.2: block sizes
-   are machine dependent and picked by measurement).  Every combination gives
-   the same results bit for bit; only the speed differs. */
+   are machine dependent and picked by measurement).  The matrix-core shapes
+   give the same results bit for bit; the vector path adds the same terms in
+   another order (results equal to rounding, about 1e-15 relative). */
 typedef struct sht_tuning {
     int synth_ncb;      /* synthesis: 16-column blocks per wavefront (1 or 2) */
     int synth_mblock;   /* synthesis: consecutive m values dealt to one

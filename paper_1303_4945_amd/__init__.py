@@ -379,7 +379,7 @@ QUEUE_COST, QUEUE_MPAIRS = 0, 1
 class Batch:
     """Several plans (same spin and precision) executed as one unit: the
     Legendre analyses of all plans in one persistent launch over a shared
-    queue; each plan's Legendre synthesis (its die-aware item list) and ring
+    queue (plans on the vector path: their own launches); each plan's Legendre synthesis (its die-aware item list) and ring
     FFTs on a stream of its own between a fork and a join; on a non-default
     stream the launches are captured once into a HIP graph per direction
     (captured again when the buffers, the stream or a plan's tuning change)

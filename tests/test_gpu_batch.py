@@ -1,5 +1,5 @@
-"""Batches of plans (persistent Legendre kernels over a cost-ordered queue,
-HIP-graph replay) and the autotuner, on the GPU.
+"""Batches of plans (a persistent Legendre analysis over a shared queue, per-plan
+chains on concurrent streams, HIP-graph replay) and the autotuner, on the GPU.
 
 A batch item runs the same per-item arithmetic as the plan's own launch, so
 batch results must equal the single-plan results bit for bit; one plan of
@@ -112,7 +112,7 @@ def test_batch_rejects_mixed_spin():
 
 def test_mixed_lmax_workload_batch():
     """The mixed batch workload: GL grids for lmax 255/511/1023/2047 with 16
-    scalar transforms each, one persistent launch per direction; equal to the
+    scalar transforms each, one persistent analysis launch; equal to the
     single plans, and the lmax 255 plan checked against the oracle on sampled
     rings and m values."""
     import torch
