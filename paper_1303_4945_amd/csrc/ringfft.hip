@@ -1300,7 +1300,15 @@ struct FftDev {
     int nrot = 0;
     std::vector<FftGroup> groups;
     std::vector<int *> group_rows;
+    // plans with several ring-length groups run the groups' launches on
+    // concurrent streams (each group alone is too small to fill the GPU):
+    // forked from and joined back to the caller's stream with events
+    std::vector<hipStream_t> aux;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
 };
+
+constexpr int FFT_MAX_AUX = 3;   // extra streams of a plan's ring FFT step
 
 }  // namespace sht
 
@@ -1456,6 +1464,18 @@ int fft_plan_build(Plan &p)
     p.fft.nrows = (int)H.rows.size();
     p.fft.table_bytes = H.ctab.size() * sizeof(double2) + H.itab.size() * sizeof(int);
     if ((rc = prepare_groups(*D))) return rc;
+    if (D->groups.size() > 1) {
+        const int naux = (int)std::min<size_t>(D->groups.size() - 1, FFT_MAX_AUX);
+        if ((rc = check_hip(hipEventCreateWithFlags(&D->fork, hipEventDisableTiming), "fft events"))) return rc;
+        for (int i = 0; i < naux; ++i) {
+            hipStream_t st = nullptr;
+            hipEvent_t e = nullptr;
+            if ((rc = check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "fft streams"))) return rc;
+            D->aux.push_back(st);
+            if ((rc = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "fft events"))) return rc;
+            D->join.push_back(e);
+        }
+    }
     // Bluestein kernel spectra on the device
     FftView v = view_of(p, *D);
     for (int li = 0; li < (int)H.lens.size(); ++li) {
@@ -1503,6 +1523,9 @@ void fft_plan_free(FftPlan &f)
     dev_free(D->itab); dev_free(D->ofs); dev_free(D->weight); dev_free(D->rot);
     dev_free(D->mvalid);
     for (int *r : D->group_rows) dev_free(r);
+    for (hipStream_t st : D->aux) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : D->join) (void)hipEventDestroy(e);
+    if (D->fork) (void)hipEventDestroy(D->fork);
     delete D;
     f.d_rows = nullptr;
 }
@@ -1557,15 +1580,46 @@ static int launch_group_anal(const FftView &v, const FftGroup &gr, const int *ro
     return SHT_OK;
 }
 
-int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_weights, hipStream_t s)
+// Stream of group i: the caller's stream for the first, the plan's extra
+// streams round robin for the others (after fft_fork).
+static hipStream_t group_stream(const FftDev &D, size_t i, hipStream_t s)
+{
+    const size_t n = D.aux.size() + 1;
+    return (i % n == 0) ? s : D.aux[i % n - 1];
+}
+
+static int fft_fork(const FftDev &D, hipStream_t s)
+{
+    if (D.aux.empty()) return SHT_OK;
+    int rc;
+    if ((rc = check_hip(hipEventRecord(D.fork, s), "fft fork"))) return rc;
+    for (hipStream_t st : D.aux)
+        if ((rc = check_hip(hipStreamWaitEvent(st, D.fork, 0), "fft fork"))) return rc;
+    return SHT_OK;
+}
+
+static int fft_join(const FftDev &D, hipStream_t s)
+{
+    int rc;
+    for (size_t j = 0; j < D.aux.size(); ++j) {
+        if ((rc = check_hip(hipEventRecord(D.join[j], D.aux[j]), "fft join"))) return rc;
+        if ((rc = check_hip(hipStreamWaitEvent(s, D.join[j], 0), "fft join"))) return rc;
+    }
+    return SHT_OK;
+}
+
+int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_weights, hipStream_t s0)
 {
     const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
     const FftView v = view_of(p, *D);
     const int ntc = p.ntrans * p.ncomp;
     const int usew = use_weights ? 1 : 0;
+    int rc0;
+    if ((rc0 = fft_fork(*D, s0))) return rc0;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
+        const hipStream_t s = group_stream(*D, i, s0);
         int rc;
         // split Bluestein always has a power-of-two inner length
         if (gr.mode == KMODE_SPLIT) rc = launch_group_synth<KMODE_SPLIT, true>(v, gr, rows, phase, map, ntc, usew, s);
@@ -1575,18 +1629,22 @@ int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_
         else rc = launch_group_synth<KMODE_LDS, false>(v, gr, rows, phase, map, ntc, usew, s);
         if (rc) return rc;
     }
-    return check_hip(hipGetLastError(), "ring synthesis launch");
+    if ((rc0 = check_hip(hipGetLastError(), "ring synthesis launch"))) return rc0;
+    return fft_join(*D, s0);
 }
 
-int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights, hipStream_t s)
+int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights, hipStream_t s0)
 {
     const FftDev *D = reinterpret_cast<const FftDev *>(p.fft.d_rows);
     const FftView v = view_of(p, *D);
     const int ntc = p.ntrans * p.ncomp;
     const int uw = use_weights ? 1 : 0;
+    int rc0;
+    if ((rc0 = fft_fork(*D, s0))) return rc0;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
+        const hipStream_t s = group_stream(*D, i, s0);
         int rc;
         if (gr.mode == KMODE_SPLIT) rc = launch_group_anal<KMODE_SPLIT, true>(v, gr, rows, map, phase, ntc, uw, s);
         else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_anal<KMODE_RADER, true>(v, gr, rows, map, phase, ntc, uw, s);
@@ -1595,7 +1653,8 @@ int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_w
         else rc = launch_group_anal<KMODE_LDS, false>(v, gr, rows, map, phase, ntc, uw, s);
         if (rc) return rc;
     }
-    return check_hip(hipGetLastError(), "ring analysis launch");
+    if ((rc0 = check_hip(hipGetLastError(), "ring analysis launch"))) return rc0;
+    return fft_join(*D, s0);
 }
 
 // Zeroes the phase entries above each ring's last kept m (the terms the polar
