@@ -433,6 +433,8 @@ def run_hp2048(args):
                        "lmax": lmax, "spin": 0, "ntrans": 8})
     out["metric"] = "loss+gradient evaluations (forward + adjoint) per second, per map"
     out["kernels_ms"] = {"fp64_pair_stages": k}
+    dom = max(("legendre_synth", "legendre_anal"), key=lambda n: k[n])
+    out["roofline"] = roofline_record(p, k, dom)
     out["legendre_fp64"] = legendre_fracs(p, k)
     out["ring_fft_hbm"] = fft_hbm(p, k)
     return out
