@@ -1580,17 +1580,33 @@ static int launch_group_anal(const FftView &v, const FftGroup &gr, const int *ro
     return SHT_OK;
 }
 
-// Stream of group i: the caller's stream for the first, the plan's extra
-// streams round robin for the others (after fft_fork).
-static hipStream_t group_stream(const FftDev &D, size_t i, hipStream_t s)
+// Whether the groups run on the plan's extra streams: only for plain launches.
+// A caller's stream under capture keeps every group (serial launches): a batch
+// capture that also forked the groups onto these streams ended in a host-side
+// crash inside the runtime, whose cause was not established.
+static bool fft_concurrent(const FftDev &D, hipStream_t s)
 {
+    if (D.aux.empty()) return false;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return st == hipStreamCaptureStatusNone;
+}
+
+// Stream of group i: the caller's stream for the first, the plan's extra
+// streams round robin for the others (after fft_fork; conc = fft_concurrent).
+static hipStream_t group_stream(const FftDev &D, size_t i, hipStream_t s, bool conc)
+{
+    if (!conc) return s;
     const size_t n = D.aux.size() + 1;
     return (i % n == 0) ? s : D.aux[i % n - 1];
 }
 
-static int fft_fork(const FftDev &D, hipStream_t s)
+static int fft_fork(const FftDev &D, hipStream_t s, bool conc)
 {
-    if (D.aux.empty()) return SHT_OK;
+    if (!conc) return SHT_OK;
     int rc;
     if ((rc = check_hip(hipEventRecord(D.fork, s), "fft fork"))) return rc;
     for (hipStream_t st : D.aux)
@@ -1598,8 +1614,9 @@ static int fft_fork(const FftDev &D, hipStream_t s)
     return SHT_OK;
 }
 
-static int fft_join(const FftDev &D, hipStream_t s)
+static int fft_join(const FftDev &D, hipStream_t s, bool conc)
 {
+    if (!conc) return SHT_OK;
     int rc;
     for (size_t j = 0; j < D.aux.size(); ++j) {
         if ((rc = check_hip(hipEventRecord(D.join[j], D.aux[j]), "fft join"))) return rc;
@@ -1614,12 +1631,13 @@ int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_
     const FftView v = view_of(p, *D);
     const int ntc = p.ntrans * p.ncomp;
     const int usew = use_weights ? 1 : 0;
+    const bool conc = fft_concurrent(*D, s0);
     int rc0;
-    if ((rc0 = fft_fork(*D, s0))) return rc0;
+    if ((rc0 = fft_fork(*D, s0, conc))) return rc0;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
-        const hipStream_t s = group_stream(*D, i, s0);
+        const hipStream_t s = group_stream(*D, i, s0, conc);
         int rc;
         // split Bluestein always has a power-of-two inner length
         if (gr.mode == KMODE_SPLIT) rc = launch_group_synth<KMODE_SPLIT, true>(v, gr, rows, phase, map, ntc, usew, s);
@@ -1630,7 +1648,7 @@ int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_
         if (rc) return rc;
     }
     if ((rc0 = check_hip(hipGetLastError(), "ring synthesis launch"))) return rc0;
-    return fft_join(*D, s0);
+    return fft_join(*D, s0, conc);
 }
 
 int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_weights, hipStream_t s0)
@@ -1639,12 +1657,13 @@ int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_w
     const FftView v = view_of(p, *D);
     const int ntc = p.ntrans * p.ncomp;
     const int uw = use_weights ? 1 : 0;
+    const bool conc = fft_concurrent(*D, s0);
     int rc0;
-    if ((rc0 = fft_fork(*D, s0))) return rc0;
+    if ((rc0 = fft_fork(*D, s0, conc))) return rc0;
     for (size_t i = 0; i < D->groups.size(); ++i) {
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
-        const hipStream_t s = group_stream(*D, i, s0);
+        const hipStream_t s = group_stream(*D, i, s0, conc);
         int rc;
         if (gr.mode == KMODE_SPLIT) rc = launch_group_anal<KMODE_SPLIT, true>(v, gr, rows, map, phase, ntc, uw, s);
         else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_anal<KMODE_RADER, true>(v, gr, rows, map, phase, ntc, uw, s);
@@ -1654,7 +1673,7 @@ int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_w
         if (rc) return rc;
     }
     if ((rc0 = check_hip(hipGetLastError(), "ring analysis launch"))) return rc0;
-    return fft_join(*D, s0);
+    return fft_join(*D, s0, conc);
 }
 
 // Zeroes the phase entries above each ring's last kept m (the terms the polar
