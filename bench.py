@@ -333,7 +333,9 @@ def run_gl4095s2(args):
         leg1 = k1["legendre_synth"] + k1["legendre_anal"]
         leg16 = k64["legendre_synth"] + k64["legendre_anal"]
         j1 = {"j16_pair_ms": ms64, "j1_pair_ms_x16": 16 * ms1, "pair_speedup": 16 * ms1 / ms64,
-              "j16_legendre_ms": leg16, "j1_legendre_ms_x16": 16 * leg1, "legendre_speedup": 16 * leg1 / leg16}
+              "j16_legendre_ms": leg16, "j1_legendre_ms_x16": 16 * leg1, "legendre_speedup": 16 * leg1 / leg16,
+              "j1_legendre_kernels": "vector units" if p1.tuning()["valu"] else "matrix cores",
+              "j1_legendre_synth_ms": k1["legendre_synth"], "j1_legendre_anal_ms": k1["legendre_anal"]}
         del p1
     torch.cuda.empty_cache()
 

@@ -295,9 +295,9 @@ typedef struct sht_tuning {
     int anal_ncb;       /* analysis: 16-column blocks per work group (1 or 2) */
     int anal_tpw;       /* analysis: slot tiles per wavefront and pass (1 or 2) */
     int valu;           /* 1: products on the vector units instead of the matrix
-                           cores (spin 0 and SHT_FP64 only; the default for one
-                           or two transforms, where most matrix-core columns
-                           would be empty) */
+                           cores (SHT_FP64 only; the default where most
+                           matrix-core columns would be empty: spin 0 with one
+                           or two transforms, spin > 0 with one) */
     int reserved[11];
 } sht_tuning;
 

@@ -523,9 +523,9 @@ int sht_autotune(sht_plan *h, double budget_seconds)
         }
         if (spent() > budget_seconds) break;
     }
-    // vector-unit kernels (spin 0, FP64) against the best matrix-core shape,
-    // on the time of one synthesis plus one analysis
-    if (!rc && p->spin == 0 && p->precision == SHT_FP64) {
+    // vector-unit kernels (FP64) against the best matrix-core shape, on the
+    // time of one synthesis plus one analysis
+    if (!rc && p->precision == SHT_FP64) {
         double pair_ms[2] = {1e300, 1e300};
         for (int vv = 0; vv < 2 && !rc; ++vv) {
             sht_tuning c = best;

@@ -982,17 +982,18 @@ __global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_ana
 //     (permlane32/16 swaps, a DPP mirror) and whose last steps add DPP copies;
 //     the wavefronts' sums are added in LDS in a fixed order (deterministic).
 
-// One step of a spin-0 chain with the staged coefficients q = (alpha, beta,
-// alpha + beta - 2, -) of the degree.
-template <bool DIFF>
+// One step of a chain with the staged coefficients q = (alpha, beta,
+// alpha + beta - 2, alpha - beta - 2) of the degree; MINUS: the -s chain of a
+// spin transform (beta and the difference-form constant of the other sign).
+template <bool DIFF, bool MINUS = false>
 __device__ __forceinline__ void chain_step(Chain &c, const double4 q)
 {
     if (DIFF) {
-        const double eps = fma(q.x, c.ms2, q.z);
+        const double eps = fma(q.x, c.ms2, MINUS ? q.w : q.z);
         c.aux = fma(eps, c.mu, c.aux);
         c.mu += c.aux;
     } else {
-        const double nx = fma(fma(q.x, c.x, q.y), c.mu, -c.aux);
+        const double nx = fma(fma(q.x, c.x, MINUS ? -q.y : q.y), c.mu, -c.aux);
         c.aux = c.mu;
         c.mu = nx;
     }
@@ -1005,10 +1006,11 @@ __device__ __forceinline__ void chain_step(Chain &c, const double4 q)
 // coefficients in .q), then gend(g) at the end of the group.  Only the G
 // degrees of a group are unrolled, so the caller's registers are indexed by u
 // alone and the compiler cannot keep the mu of the whole chunk alive.
-template <int LC, int G, int K, bool DIFF, typename Load, typename Emit, typename GroupEnd>
+template <int LC, int G, int K, bool DIFF, int NCH, typename Load, typename Emit, typename GroupEnd>
 __device__ __forceinline__ void chains_chunk(Chain (&c)[K], bool &slow, int l0, int lc, int lmax, double thr,
                                              double down, Load load, Emit emit, GroupEnd gend)
 {
+    // K chains; with NCH = 2 chain k is the (k % 2 ? -s : +s) chain of slot k / 2
     static_assert(LC % G == 0, "whole groups");
     if (!slow && lc >= l0 && lc + LC <= lmax) {
         // every degree steps and every chain is at scale 0: no masks
@@ -1020,7 +1022,8 @@ __device__ __forceinline__ void chains_chunk(Chain (&c)[K], bool &slow, int l0, 
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     emit(u, k, c[k].mu, d);
-                    chain_step<DIFF>(c[k], d.q);
+                    if (NCH == 2 && (k & 1)) chain_step<DIFF, true>(c[k], d.q);
+                    else chain_step<DIFF>(c[k], d.q);
                 }
             }
             gend(g);
@@ -1045,7 +1048,8 @@ __device__ __forceinline__ void chains_chunk(Chain (&c)[K], bool &slow, int l0, 
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     emit(u, k, c[k].mu * on[k], d);
-                    chain_step<DIFF>(c[k], d.q);
+                    if (NCH == 2 && (k & 1)) chain_step<DIFF, true>(c[k], d.q);
+                    else chain_step<DIFF>(c[k], d.q);
                 }
             }
         } else {
@@ -1057,7 +1061,10 @@ __device__ __forceinline__ void chains_chunk(Chain (&c)[K], bool &slow, int l0, 
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     emit(u, k, in ? c[k].mu * on[k] : 0.0, d);
-                    if (steps) chain_step<DIFF>(c[k], d.q);
+                    if (steps) {
+                        if (NCH == 2 && (k & 1)) chain_step<DIFF, true>(c[k], d.q);
+                        else chain_step<DIFF>(c[k], d.q);
+                    }
                 }
             }
         }
@@ -1078,14 +1085,15 @@ __device__ __forceinline__ void chains_chunk(Chain (&c)[K], bool &slow, int l0, 
 
 // chains of the K slots of this lane (tile[k] < 0: none), the form (difference
 // form if any slot of the wave is close to a pole) and the scale flag
-template <int K>
-__device__ __forceinline__ void chains_init(const LegView &v, int m, const int (&tile)[K], int lane, Chain (&c)[K],
-                                            bool &diff, bool &slow)
+template <int K, int NCH = 1>
+__device__ __forceinline__ void chains_init(const LegView &v, int m, const int (&tile)[K], int lane,
+                                            Chain (&c)[K * NCH], bool &diff, bool &slow)
 {
     bool d = false, s = false;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        c[k] = chain_init(v, m, tile[k] >= 0 ? tile[k] * 64 + lane : v.nslots, 0);
+    for (int k = 0; k < K * NCH; ++k) {
+        const int kt = k / NCH;
+        c[k] = chain_init(v, m, tile[kt] >= 0 ? tile[kt] * 64 + lane : v.nslots, k % NCH);
         d = d || c[k].x > DIFF_FORM_COS;
         s = s || c[k].k < 0;
     }
@@ -1093,7 +1101,7 @@ __device__ __forceinline__ void chains_init(const LegView &v, int m, const int (
     slow = wave_any(s);
     if (diff)
 #pragma unroll
-        for (int k = 0; k < K; ++k) c[k].aux = c[k].mu;
+        for (int k = 0; k < K * NCH; ++k) c[k].aux = c[k].mu;
 }
 
 constexpr int VSYN_LC = 16;   // degrees per chunk of the vector synthesis
@@ -1177,7 +1185,7 @@ __global__ __launch_bounds__(64) void k_legendre_synth_valu(LegView v, const Wav
             const int buf = chunk & 1;
             const bool more = lc + LC <= lmax;
             if (more) fetch(lc + LC);
-            chains_chunk<LC, 4, K, DIFF>(
+            chains_chunk<LC, 4, K, DIFF, 1>(
                 cs, slow, l0, lc, lmax, thr, down, [&](int t) -> const SynStage<J> & { return st[buf][t]; },
                 [&](int u, int k, double mu, const SynStage<J> &d) {
 #pragma unroll
@@ -1211,6 +1219,164 @@ __global__ __launch_bounds__(64) void k_legendre_synth_valu(LegView v, const Wav
             const double2 a0 = acc[0][k][tr], a1 = acc[1][k][tr];
             if (yn >= 0) ph[(rowbase + yn) * (v.mmax + 1) + m] = make_double2(a0.x + a1.x, a0.y + a1.y);
             if (ys >= 0) ph[(rowbase + ys) * (v.mmax + 1) + m] = make_double2(a0.x - a1.x, a0.y - a1.y);
+        }
+    }
+}
+
+// staged data of one degree of the spin vector synthesis
+template <int J>
+struct SynStageS {
+    double4 q;        // step coefficients: alpha, beta, delta+, delta- (the -s chain takes -beta, delta-)
+    double4 co[J];    // c f_l (E_re, E_im, B_re, B_im) per transform, c = 1/2 (zero outside [l0, lmax])
+};
+
+// Spin s > 0, work item (m, K units of 64 slots from slot 32 it.tile, J
+// transforms): a lane runs the +s and -s chains of K ring slots.  Per degree and slot W = -(mu_+ + mu_-) and
+// X = mu_+ - mu_- (the -s chain carries (-1)^s), and per transform
+//   Q_re += W E_re + X B_im,   Q_im += W E_im - X B_re,
+//   U_re += W B_re - X E_im,   U_im += W B_im + X E_re
+// (E, B times c f_l), the W terms into the class of the degree's l + m parity
+// and the X terms into the other (their mirror-ring signs are opposite); ring
+// t gets A0 + A1, ring pi - t gets (-1)^s (A0 - A1).  Derivative synthesis
+// (spin-1 plan): one input component per transform, E = sqrt(l (l + 1)) a_lm
+// and B = 0.
+template <int J, int K>
+__global__ __launch_bounds__(64) void k_legendre_synth_valu_s(LegView v, const WaveItem *__restrict__ items,
+                                                              const double *__restrict__ alm,
+                                                              double *__restrict__ phase, int deriv)
+{
+    constexpr int LC = VSYN_LC;
+    __shared__ SynStageS<J> st[2][LC];
+    const WaveItem it = items[blockIdx.x];
+    if (it.m < 0) return;
+    const int lane = threadIdx.x;
+    const int m = it.m, t0 = it.t0, lmax = v.lmax;
+    const int l0 = v.spin > m ? v.spin : m;
+    const int lstart = l0 - ((l0 + m) & 1);   // l + m even at every chunk start: class of offset t = t & 1
+    const double sig = (v.spin & 1) ? -1.0 : 1.0;
+    const double4 *coef = v.coef + v.coef_ofs[m];
+    const double *flm = v.fl + v.coef_ofs[m];
+    const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
+    const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
+    // units of 64 consecutive slots (two 32-slot tiles; items start at even tiles)
+    int tile[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int u = (it.tile >> 1) + k;
+        tile[k] = u * 64 < v.nslots ? u : -1;
+    }
+    Chain cs[2 * K];   // chain 2k: +s of slot k, 2k + 1: -s
+    bool diff, slow;
+    chains_init<K, 2>(v, m, tile, lane, cs, diff, slow);
+    const int ncin = deriv ? 1 : 2;   // input components per transform
+
+    // lane t < LC fetches degree lc + t of a chunk (clamped addresses; masked when staged)
+    double4 nq;
+    double nf, nd = 1.0;
+    double2 nE[J], nB[J];
+    auto fetch = [&](int lc) {
+        const int l = lc + (lane % LC);
+        const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+        nq = coef[lcl];
+        nf = flm[lcl];
+        if (deriv) nd = v.dfac[lcl];
+#pragma unroll
+        for (int tr = 0; tr < J; ++tr) {
+            const int t = t0 + tr < v.ntrans ? t0 + tr : 0;
+            const double2 *er = reinterpret_cast<const double2 *>(alm) + (int64_t)t * ncin * v.nalm + mbase;
+            nE[tr] = er[lcl];
+            nB[tr] = deriv ? make_double2(0.0, 0.0) : er[v.nalm + lcl];
+        }
+    };
+    auto stage = [&](int buf, int lc) {
+        if (lane < LC) {
+            const int l = lc + lane;
+            SynStageS<J> e;
+            e.q = (l >= l0 && l < lmax) ? nq : double4{0, 0, 0, 0};
+            const double f = (l >= l0 && l <= lmax) ? 0.5 * nf * nd : 0.0;
+            const double fi = m == 0 ? 0.0 : f;   // Im a_l0 takes no part
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr)
+                e.co[tr] = (t0 + tr < v.ntrans) ? double4{nE[tr].x * f, nE[tr].y * fi, nB[tr].x * f, nB[tr].y * fi}
+                                                : double4{0, 0, 0, 0};
+            st[buf][lane] = e;
+        }
+    };
+
+    double4 acc[2][K][J];   // class, slot, transform: (Q_re, Q_im, U_re, U_im)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) acc[p][k][tr] = double4{0, 0, 0, 0};
+    fetch(lstart);
+    stage(0, lstart);
+    wave_sync();
+    double mu_p[K];   // the +s chain's value of the current degree (emitted before the -s chain)
+    auto run = [&](auto form) {
+        constexpr bool DIFF = decltype(form)::value;
+        int chunk = 0;
+        for (int lc = lstart; lc <= lmax; lc += LC, ++chunk) {
+            const int buf = chunk & 1;
+            const bool more = lc + LC <= lmax;
+            if (more) fetch(lc + LC);
+            chains_chunk<LC, 4, 2 * K, DIFF, 2>(
+                cs, slow, l0, lc, lmax, thr, down, [&](int t) -> const SynStageS<J> & { return st[buf][t]; },
+                [&](int u, int kc, double mu, const SynStageS<J> &d) {
+                    const int k = kc >> 1;
+                    if (!(kc & 1)) {
+                        mu_p[k] = mu;
+                        return;
+                    }
+                    const double w = -(mu_p[k] + mu), x = mu_p[k] - mu;
+                    const int cw = u & 1, cx = cw ^ 1;   // groups of four degrees from an even offset
+#pragma unroll
+                    for (int tr = 0; tr < J; ++tr) {
+                        const double4 c = d.co[tr];
+                        double4 &aw = acc[cw][k][tr];
+                        double4 &ax = acc[cx][k][tr];
+                        aw.x = fma(w, c.x, aw.x);
+                        aw.y = fma(w, c.y, aw.y);
+                        aw.z = fma(w, c.z, aw.z);
+                        aw.w = fma(w, c.w, aw.w);
+                        ax.x = fma(x, c.w, ax.x);
+                        ax.y = fma(-x, c.z, ax.y);
+                        ax.z = fma(-x, c.y, ax.z);
+                        ax.w = fma(x, c.x, ax.w);
+                    }
+                },
+                [](int) {});
+            wave_sync();   // this chunk's reads of the other buffer are issued
+            if (more) stage(buf ^ 1, lc + LC);
+            wave_sync();
+        }
+    };
+    if (diff) run(std::true_type{});
+    else run(std::false_type{});
+
+    // ring t = A0 + A1, ring pi - t = (-1)^s (A0 - A1); component 0: Q, 1: U
+    double2 *ph = reinterpret_cast<double2 *>(phase);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (tile[k] < 0) continue;
+        const int slot = tile[k] * 64 + lane;
+        if (slot >= v.nslots) continue;
+        const int yn = v.slot_yn[slot], ys = v.slot_ys[slot];
+#pragma unroll
+        for (int tr = 0; tr < J; ++tr) {
+            const int t = t0 + tr;
+            if (t >= v.ntrans) break;
+            const double4 a0 = acc[0][k][tr], a1 = acc[1][k][tr];
+            const int64_t rq = (int64_t)t * 2 * v.nrings, ru = rq + v.nrings;
+            if (yn >= 0) {
+                ph[(rq + yn) * (v.mmax + 1) + m] = make_double2(a0.x + a1.x, a0.y + a1.y);
+                ph[(ru + yn) * (v.mmax + 1) + m] = make_double2(a0.z + a1.z, a0.w + a1.w);
+            }
+            if (ys >= 0) {
+                ph[(rq + ys) * (v.mmax + 1) + m] = make_double2(sig * (a0.x - a1.x), sig * (a0.y - a1.y));
+                ph[(ru + ys) * (v.mmax + 1) + m] = make_double2(sig * (a0.z - a1.z), sig * (a0.w - a1.w));
+            }
         }
     }
 }
@@ -1433,8 +1599,8 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
                 for (int i = 0; i < 8; ++i) x[i] = 0.0;
             };
             if (active) {
-                if (diff) chains_chunk<LC, GD, K, true>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
-                else chains_chunk<LC, GD, K, false>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
+                if (diff) chains_chunk<LC, GD, K, true, 1>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
+                else chains_chunk<LC, GD, K, false, 1>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
             } else {
                 for (int e = lane; e < NV; e += 64) part[buf][wave][e] = 0.0;
             }
@@ -1453,6 +1619,200 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
             }
             // part[buf] and stq[buf] are written again in the next chunk but one,
             // after the next barrier
+        }
+        first = false;
+    }
+}
+
+// Spin s > 0 analysis (transposed column maps of the spin synthesis): per
+// degree and slot W = -(mu_+ + mu_-), X = mu_+ - mu_-, and per transform
+//   E_re += W GW_Qre + X GX_Uim,   E_im += W GW_Qim - X GX_Ure,
+//   B_re += W GW_Ure - X GX_Qim,   B_im += W GW_Uim + X GX_Qre,
+// with GW the stationary phases of the degree's class (G_t + (-1)^s G_(pi-t) at
+// l + m even, G_t - (-1)^s G_(pi-t) at odd) and GX those of the other class;
+// the sums times c f_l (c = 1/2).  Work groups, passes and the butterfly as in
+// the spin-0 kernel (4 values per degree and transform), the slots dealt in
+// units of 64 (two 32-slot tiles).  Adjoint of the derivative synthesis: E
+// alone, times sqrt(l (l + 1)), one output component per transform.
+template <int J, int K>
+__global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu_s(LegView v, const int *__restrict__ mlist,
+                                                                     const double *__restrict__ phase,
+                                                                     double *__restrict__ alm, int mode)
+{
+    constexpr int LC = ANV_CH / (2 * J);   // degrees per chunk
+    constexpr int NV = LC * J * 4;         // output values of a chunk: (E, B) x (re, im) per transform
+    constexpr int GD = 2;                  // degrees per reduction group: 8 values (one transform)
+    static_assert(J == 1 && LC % GD == 0 && LC <= 64, "value layout");
+    constexpr int OPT = (NV + 63) / 64;
+    __shared__ double part[2][ANV_NW][NV];
+    __shared__ double4 stq[2][LC];
+    __shared__ double stf[2][LC];
+    const int m = mlist[blockIdx.x];
+    const int t0 = (int)blockIdx.y * J;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nw = (int)(blockDim.x >> 6);
+    const int lmax = v.lmax;
+    const int l0 = v.spin > m ? v.spin : m;
+    const int lstart = l0 - ((l0 + m) & 1);   // l + m even at every chunk start
+    const double sig = (v.spin & 1) ? -1.0 : 1.0;
+    const double4 *coef = v.coef + v.coef_ofs[m];
+    const double *flm = v.fl + v.coef_ofs[m];
+    const int64_t mbase = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2;
+    const double thr = ldexp(1.0, v.thresh_bits), down = ldexp(1.0, -v.rescale_bits);
+    const bool grad = mode & ANA_MODE_GRAD;
+    const bool deriv = mode & ANA_MODE_DERIV;
+    const double2 *G = reinterpret_cast<const double2 *>(phase);
+    double2 *out = reinterpret_cast<double2 *>(alm);
+    const double fac = (grad && m > 0) ? 2.0 : 1.0;   // fac_m of the real-field gradient
+    // output element e: value index ((t J + tr) 2 + comp) 2 + re/im, comp 0 = E, 1 = B
+    const int ncout = deriv ? 1 : 2;
+    auto orow = [&](int e) {
+        const int tr = (e >> 2) % J, comp = (e >> 1) & 1;
+        return reinterpret_cast<double *>(out + ((int64_t)(t0 + tr) * ncout + comp) * v.nalm + mbase) + (e & 1);
+    };
+    auto o_valid = [&](int e) {
+        return e < NV && t0 + (e >> 2) % J < v.ntrans && !(deriv && ((e >> 1) & 1));
+    };
+
+    // degrees m .. l0 - 1 (spin s > m) are zero by convention
+    for (int e = tid; e < (l0 - m) * J * 4; e += (int)blockDim.x) {
+        const int l = m + e / (J * 4), r = e % (J * 4);
+        if (o_valid(r)) orow(r)[2 * (int64_t)l] = 0.0;
+    }
+
+    // units of 64 slots: active when one of their two tiles is
+    const int nunits = (v.nslots + 63) / 64;
+    auto unit_act = [&](int u) {
+        return v.tile_mlim[2 * u] >= m || (2 * u + 1 < v.ntiles && v.tile_mlim[2 * u + 1] >= m);
+    };
+    int ntiles_act = 0;
+    for (int u = 0; u < nunits; ++u) ntiles_act += unit_act(u);
+    int tscan = 0, tcount = 0, cidx = 0;
+    bool first = true;
+    while (tcount < ntiles_act || first) {
+        int tile[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) tile[k] = -1;
+        {
+            int n = 0;
+            for (; tscan < nunits && n < nw * K; ++tscan) {
+                if (!unit_act(tscan)) continue;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (n == wave * K + k) tile[k] = tscan;
+                ++n;
+            }
+            tcount += n;
+        }
+        const bool active = tile[0] >= 0;
+        Chain cs[2 * K];
+        bool diff, slow;
+        chains_init<K, 2>(v, m, tile, lane, cs, diff, slow);
+        // stationary phases (Q_re, Q_im, U_re, U_im) of the lane's slots per class
+        double4 g[K][2][J];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int slot = tile[k] >= 0 ? tile[k] * 64 + lane : v.nslots;
+            const bool ok = slot < v.nslots;
+            const int yn = ok ? v.slot_yn[slot] : -1, ys = ok ? v.slot_ys[slot] : -1;
+#pragma unroll
+            for (int tr = 0; tr < J; ++tr) {
+                const bool tok = t0 + tr < v.ntrans;
+                const int64_t rq = (int64_t)(tok ? t0 + tr : 0) * 2 * v.nrings, ru = rq + v.nrings;
+                const int yn0 = yn >= 0 ? yn : 0, ys0 = ys >= 0 ? ys : 0;
+                const double2 qn0 = G[(rq + yn0) * (v.mmax + 1) + m], un0 = G[(ru + yn0) * (v.mmax + 1) + m];
+                const double2 qs0 = G[(rq + ys0) * (v.mmax + 1) + m], us0 = G[(ru + ys0) * (v.mmax + 1) + m];
+                const bool nok = tok && yn >= 0, sok = tok && ys >= 0;
+                const double2 qn = nok ? qn0 : make_double2(0.0, 0.0), un = nok ? un0 : make_double2(0.0, 0.0);
+                const double2 qs = sok ? make_double2(sig * qs0.x, sig * qs0.y) : make_double2(0.0, 0.0);
+                const double2 us = sok ? make_double2(sig * us0.x, sig * us0.y) : make_double2(0.0, 0.0);
+                g[k][0][tr] = double4{qn.x + qs.x, qn.y + qs.y, un.x + us.x, un.y + us.y};
+                g[k][1][tr] = double4{qn.x - qs.x, qn.y - qs.y, un.x - us.x, un.y - us.y};
+            }
+        }
+        double4 nq = double4{0, 0, 0, 0};
+        double nf = 0.0;
+        auto fetch = [&](int lc) {
+            if (wave == 0) {
+                const int l = lc + (lane % LC);
+                const int lcl = l < l0 ? l0 : (l > lmax ? lmax : l);
+                nq = coef[lcl];
+                nf = flm[lcl] * (deriv ? v.dfac[lcl] : 1.0);
+            }
+        };
+        auto stage = [&](int buf, int lc) {
+            if (wave == 0 && lane < LC) {
+                const int l = lc + lane;
+                stq[buf][lane] = (l >= l0 && l < lmax) ? nq : double4{0, 0, 0, 0};
+                stf[buf][lane] = (l >= l0 && l <= lmax) ? 0.5 * nf : 0.0;
+            }
+        };
+        fetch(lstart);
+        stage(cidx & 1, lstart);
+        __syncthreads();
+        for (int lc = lstart; lc <= lmax; lc += LC, ++cidx) {
+            const int buf = cidx & 1;
+            const bool more = lc + LC <= lmax;
+            if (more) fetch(lc + LC);
+            double prev[OPT];
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) {
+                const int e = tid + j * (int)blockDim.x;
+                const int ol = lc + (e >> 2) / J;
+                prev[j] = (!first && o_valid(e) && ol <= lmax) ? orow(e)[2 * (int64_t)ol] : 0.0;
+            }
+            // value index within a group: ((u J + tr) 2 + comp) 2 + re/im
+            double x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = 0.0;
+            double mu_p[K];
+            struct AnaD {
+                double4 q;
+            };
+            auto load = [&](int t) { return AnaD{stq[buf][t]}; };
+            auto emit = [&](int u, int kc, double mu, const AnaD &) {
+                const int k = kc >> 1;
+                if (!(kc & 1)) {
+                    mu_p[k] = mu;
+                    return;
+                }
+                const double w = -(mu_p[k] + mu), xx = mu_p[k] - mu;
+                const int cw = u & 1, cx = cw ^ 1;   // groups of two degrees from an even offset
+#pragma unroll
+                for (int tr = 0; tr < J; ++tr) {
+                    const double4 gw = g[k][cw][tr], gx = g[k][cx][tr];
+                    double *o = x + (u * J + tr) * 4;
+                    o[0] = fma(w, gw.x, fma(xx, gx.w, o[0]));    // E_re
+                    o[1] = fma(w, gw.y, fma(-xx, gx.z, o[1]));   // E_im
+                    o[2] = fma(w, gw.z, fma(-xx, gx.y, o[2]));   // B_re
+                    o[3] = fma(w, gw.w, fma(xx, gx.x, o[3]));    // B_im
+                }
+            };
+            auto gend = [&](int g0) {
+                const double r = wave_reduce8(x, lane);
+                if ((lane & 7) == 0) part[buf][wave][(g0 / GD) * 8 + (lane >> 3)] = r;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[i] = 0.0;
+            };
+            if (active) {
+                if (diff) chains_chunk<LC, GD, 2 * K, true, 2>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
+                else chains_chunk<LC, GD, 2 * K, false, 2>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
+            } else {
+                for (int e = lane; e < NV; e += 64) part[buf][wave][e] = 0.0;
+            }
+            if (more) stage(buf ^ 1, lc + LC);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) {
+                const int e = tid + j * (int)blockDim.x;
+                const int t = (e >> 2) / J, ol = lc + t;
+                if (!o_valid(e) || ol > lmax || ol < m) continue;
+                double sum = part[buf][0][e];
+                for (int w = 1; w < nw; ++w) sum += part[buf][w][e];
+                double val = sum * stf[buf][t] * fac;
+                if (m == 0 && (e & 1)) val = 0.0;
+                orow(e)[2 * (int64_t)ol] = first ? val : prev[j] + val;
+            }
         }
         first = false;
     }
@@ -1535,7 +1895,8 @@ static void dispatch_anal(const Plan &p, const LegView &v, const double *phase, 
     }
 }
 
-int valu_jpg(const Plan &p) { return p.ntrans >= 2 ? 2 : 1; }
+// transforms per work item of the vector kernels: two for spin 0, one for spin > 0
+int valu_jpg(const Plan &p) { return (p.spin == 0 && p.ntrans >= 2) ? 2 : 1; }
 
 // slot tiles per lane group of the vector kernels (K slots per lane) where the
 // plan has tiles enough to keep the waves busy, fewer for small grids:
@@ -1544,8 +1905,9 @@ int valu_jpg(const Plan &p) { return p.ntrans >= 2 ? 2 : 1; }
 // analysis 1.43 ms with four, 1.49 with two)
 int valu_k(const Plan &p, bool anal)
 {
-    const int kmax = (anal && valu_jpg(p) == 1) ? 4 : 2;
-    const int k = p.ntiles >= 8 ? 4 : (p.ntiles >= 2 ? 2 : 1);
+    const int kmax = (anal && p.spin == 0 && valu_jpg(p) == 1) ? 4 : 2;
+    const int units = (p.nslots + 63) / 64;   // 64-slot units (spin plans: two tiles each)
+    const int k = units >= 8 ? 4 : (units >= 2 ? 2 : 1);
     return k < kmax ? k : kmax;
 }
 
@@ -1568,6 +1930,24 @@ static void launch_anal_valu_t(const Plan &p, const LegView &v, const double *ph
     const int nw = groups < nwmax ? (groups > 0 ? groups : 1) : nwmax;
     const dim3 grid((unsigned)(p.mmax + 1), (unsigned)((p.ntrans + J - 1) / J));
     hipLaunchKernelGGL((k_legendre_anal_valu<J, K>), grid, dim3(64 * nw), 0, s, v, p.d_anal_ms, phase, alm, mode);
+}
+
+template <int K>
+static void launch_synth_valu_s_t(const Plan &p, const LegView &v, const double *alm, double *phase, int deriv,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL((k_legendre_synth_valu_s<1, K>), dim3((unsigned)p.synth_items.size()), dim3(64), 0, s, v,
+                       p.d_synth_items, alm, phase, deriv);
+}
+
+template <int K>
+static void launch_anal_valu_s_t(const Plan &p, const LegView &v, const double *phase, double *alm, int mode,
+                                 hipStream_t s)
+{
+    const int groups = ((p.nslots + 63) / 64 + K - 1) / K;
+    const int nw = groups < 2 ? (groups > 0 ? groups : 1) : 2;
+    const dim3 grid((unsigned)(p.mmax + 1), (unsigned)p.ntrans);
+    hipLaunchKernelGGL((k_legendre_anal_valu_s<1, K>), grid, dim3(64 * nw), 0, s, v, p.d_anal_ms, phase, alm, mode);
 }
 
 template <int J>
@@ -1593,9 +1973,14 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool 
 {
     if (p.synth_items.empty()) return SHT_OK;
     const LegView v = make_leg_view(p);
-    if (p.tune.valu) {
+    if (p.tune.valu && p.spin == 0) {
         if (valu_jpg(p) == 1) synth_valu_k<1>(p, v, alm, phase, s);
         else synth_valu_k<2>(p, v, alm, phase, s);
+        return check_hip(hipGetLastError(), "legendre synthesis launch");
+    }
+    if (p.tune.valu) {   // spin > 0
+        if (valu_k(p, false) == 2) launch_synth_valu_s_t<2>(p, v, alm, phase, deriv ? 1 : 0, s);
+        else launch_synth_valu_s_t<1>(p, v, alm, phase, deriv ? 1 : 0, s);
         return check_hip(hipGetLastError(), "legendre synthesis launch");
     }
     const int d = deriv ? 1 : 0;
@@ -1611,9 +1996,14 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool 
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s)
 {
     const LegView v = make_leg_view(p);
-    if (p.tune.valu) {
+    if (p.tune.valu && p.spin == 0) {
         if (valu_jpg(p) == 1) anal_valu_k<1>(p, v, phase, alm, mode, s);
         else anal_valu_k<2>(p, v, phase, alm, mode, s);
+        return check_hip(hipGetLastError(), "legendre analysis launch");
+    }
+    if (p.tune.valu) {   // spin > 0
+        if (valu_k(p, true) == 2) launch_anal_valu_s_t<2>(p, v, phase, alm, mode, s);
+        else launch_anal_valu_s_t<1>(p, v, phase, alm, mode, s);
         return check_hip(hipGetLastError(), "legendre analysis launch");
     }
     if (p.precision == SHT_FP32_MFMA) dispatch_anal<true>(p, v, phase, alm, mode, s);

@@ -134,15 +134,15 @@ int build_synth_items(Plan &p)
         for (int m = mb; m < std::min(p.mmax + 1, mb + MB); ++m) {
             const double lrange = (double)(p.lmax + 1 - std::max(m, p.spin));
             // one item per active slot tile, or (vector path) per group of K
-            // consecutive tiles with an active one
-            const int tstep = p.tune.valu ? valu_k(p, false) : 1;
+            // consecutive 64-slot units with an active tile
+            const int tstep = p.tune.valu ? valu_k(p, false) * (64 / p.slots_per_tile) : 1;
             for (int t = 0; t < p.ntiles; t += tstep) {
                 bool act = false;
                 for (int u = t; u < std::min(p.ntiles, t + tstep); ++u) act = act || p.tile_mlim[u] >= m;
                 if (!act) continue;
                 for (int gI = 0; gI < ngroups; ++gI) {
                     blk.push_back(WaveItem{m, t, gI * jpg, 0});
-                    cost += lrange * tstep;
+                    cost += lrange * tstep * p.slots_per_tile;
                 }
             }
         }
@@ -256,7 +256,9 @@ sht_tuning default_tuning(const Plan &p)
     t.synth_mblock = 4;
     t.anal_ncb = anal_ncb(p.spin, p.ntrans);
     t.anal_tpw = anal_tpw_built(p.spin, t.anal_ncb);
-    t.valu = (p.spin == 0 && p.precision == SHT_FP64 && p.ntrans <= 2) ? 1 : 0;
+    // vector units where most matrix-core columns would be empty: one or two
+    // spin-0 transforms (2 or 4 of 16 columns), one spin transform (4 of 16)
+    t.valu = (p.precision == SHT_FP64 && ((p.spin == 0 && p.ntrans <= 2) || (p.spin > 0 && p.ntrans == 1))) ? 1 : 0;
     return t;
 }
 
@@ -278,8 +280,8 @@ int tuning_check(const Plan &p, const sht_tuning &t)
         set_error("valu must be 0 or 1");
         return SHT_EUNSUPPORTED;
     }
-    if (t.valu && (p.spin != 0 || p.precision != SHT_FP64)) {
-        set_error("the vector-unit kernels are built for spin 0 and SHT_FP64 only");
+    if (t.valu && p.precision != SHT_FP64) {
+        set_error("the vector-unit kernels are built for SHT_FP64 only");
         return SHT_EUNSUPPORTED;
     }
     if (t.anal_tpw != anal_tpw_built(p.spin, t.anal_ncb)) {

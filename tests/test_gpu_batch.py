@@ -234,15 +234,22 @@ def test_autotune_keeps_results_and_writes_cache(tmp_path):
         p = sht.Plan(sht.Geometry.from_inputs(g), 127, spin=2, ntrans=8)
         a = to_dev(si.random_alm(127, 127, 8, 2, tag=5))
         before = to_host(p.alm2map(a))
+        valu0 = p.tuning()["valu"]
         p.autotune(2.0)
         after = to_host(p.alm2map(a))
-        assert np.array_equal(before, after)
+        # matrix-core shapes: the same sums bit for bit; a switch to the vector
+        # units: the same terms in another order
+        if p.tuning()["valu"] == valu0:
+            assert np.array_equal(before, after)
+        else:
+            assert rel_err(after, before) < 1e-13
         text = (tmp_path / "tune.txt").read_text()
         assert "lmax=127" in text and "spin=2" in text
         # a second plan of the same shape takes the cached choice without timing
         p2 = sht.Plan(sht.Geometry.from_inputs(g), 127, spin=2, ntrans=8)
         p2.autotune(0.0)
-        assert np.array_equal(to_host(p2.alm2map(a)), before)
+        assert p2.tuning() == p.tuning()
+        assert np.array_equal(to_host(p2.alm2map(a)), after)
     finally:
         del os.environ["SHT_TUNE_CACHE"]
 

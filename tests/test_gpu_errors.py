@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import sht_inputs as si
-from gpu_util import to_dev, to_host
+from gpu_util import rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -155,4 +155,9 @@ def test_batch_graph_recaptured_after_member_retuned(tmp_path):
             b.alm2map(a, outs=outs, stream=s)
             s.synchronize()
             assert np.array_equal(to_host(outs[0]), to_host(p.alm2map(a[0])))
-    assert np.array_equal(to_host(outs[0]), ref)
+    # the matrix-core shapes give the same sums bit for bit; the vector units
+    # (a choice the timed run may make) the same terms in another order
+    if p.tuning()["valu"] == before["valu"]:
+        assert np.array_equal(to_host(outs[0]), ref)
+    else:
+        assert rel_err(to_host(outs[0]), ref) < 1e-13

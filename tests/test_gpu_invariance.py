@@ -50,38 +50,47 @@ def test_polar_skip_does_not_change_results(spin):
 
 
 def test_rescale_step_invariance():
+    """Matrix-core kernels (the scale checked per degree): rounding level from
+    S = 128 on, ~1e-10 at S = 64."""
     sht = _sht()
     lmax = 1023
     g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
     geom = sht.Geometry.from_inputs(g)
     a = to_dev(si.random_alm(lmax, lmax, 1, 2, tag=42))
-    ref = to_host(sht.Plan(geom, lmax, spin=2, rescale_bits=256).alm2map(a))
+
+    def plan(bits):
+        p = sht.Plan(geom, lmax, spin=2, rescale_bits=bits)
+        p.set_tuning(valu=0)
+        return p
+
+    ref = to_host(plan(256).alm2map(a))
     for bits in (128, 400, 640):
-        got = to_host(sht.Plan(geom, lmax, spin=2, rescale_bits=bits).alm2map(a))
+        got = to_host(plan(bits).alm2map(a))
         assert rel_err(got, ref) < 1e-13, bits
-    got = to_host(sht.Plan(geom, lmax, spin=2, rescale_bits=64).alm2map(a))
+    got = to_host(plan(64).alm2map(a))
     assert rel_err(got, ref) < 1e-9
 
 
-def test_rescale_step_invariance_vector_path():
-    """The vector-unit kernels (spin 0, one transform) check a chain's scale
-    once per group of four degrees, so a chain enters up to three degrees late:
-    the terms left out are below 2^-(S/2) 3^4 relative, rounding level from
-    S = 128 on and ~1e-8 at S = 64."""
+@pytest.mark.parametrize("spin", [0, 2])
+def test_rescale_step_invariance_vector_path(spin):
+    """The vector-unit kernels (one transform) check a chain's scale once per
+    group of four degrees (spin-s analysis: two), so a chain enters up to three
+    degrees late: the terms left out are below 2^-(S/2) 3^4 relative, rounding
+    level from S = 128 on and ~1e-8 at S = 64."""
     sht = _sht()
     lmax = 1023
     g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
     geom = sht.Geometry.from_inputs(g)
-    a = to_dev(si.random_alm(lmax, lmax, 1, 0, tag=44))
-    ref_p = sht.Plan(geom, lmax, spin=0, rescale_bits=256)
+    a = to_dev(si.random_alm(lmax, lmax, 1, spin, tag=44))
+    ref_p = sht.Plan(geom, lmax, spin=spin, rescale_bits=256)
     assert ref_p.tuning()["valu"] == 1
     ref = to_host(ref_p.alm2map(a))
     back_ref = to_host(ref_p.map2alm(to_dev(ref)))
     for bits in (128, 400, 640):
-        p = sht.Plan(geom, lmax, spin=0, rescale_bits=bits)
+        p = sht.Plan(geom, lmax, spin=spin, rescale_bits=bits)
         assert rel_err(to_host(p.alm2map(a)), ref) < 1e-13, bits
         assert rel_err(to_host(p.map2alm(to_dev(ref))), back_ref) < 1e-13, bits
-    p = sht.Plan(geom, lmax, spin=0, rescale_bits=64)
+    p = sht.Plan(geom, lmax, spin=spin, rescale_bits=64)
     assert rel_err(to_host(p.alm2map(a)), ref) < 1e-7
     assert rel_err(to_host(p.map2alm(to_dev(ref))), back_ref) < 1e-7
 

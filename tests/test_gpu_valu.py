@@ -1,7 +1,7 @@
-"""The vector-unit Legendre kernels (spin 0, one or two transforms: the
-default there) against the oracle and against the matrix-core kernels of the
-same plan (set through the tuning), including the gradient mode, batches and
-ragged sizes."""
+"""The vector-unit Legendre kernels (spin 0 with one or two transforms and
+spin > 0 with one: the default there) against the oracle and against the
+matrix-core kernels of the same plan (set through the tuning), including the
+gradient mode, the derivative maps, batches and ragged sizes."""
 import numpy as np
 import pytest
 
@@ -78,10 +78,76 @@ def test_valu_batch_equals_plans():
         assert np.array_equal(to_host(ab), to_host(p.map2alm(mp)))
 
 
+SPIN_CASES = {
+    # name: (geometry, lmax, mmax, spin, ntrans)
+    "s2_gl": (lambda: si.gauss_geometry(48, 95, 0.2), 47, 47, 2, 1),
+    "s1_hp_j2": (lambda: si.healpix_geometry(16), 40, 40, 1, 2),
+    "s3_mmax": (lambda: si.gauss_geometry(30, 61, 0.1), 29, 20, 3, 1),   # l0 = s > m at m < 3
+    "s37_gl": (lambda: si.gauss_geometry(64, 129, 0.3), 63, 63, 37, 1),
+    "s2_unpaired_j3": (lambda: si.ecp_geometry(17, 41, si.ECP_FEJER1, 0.4), 20, 18, 2, 3),
+    # many rings at a small lmax: two 64-slot units per lane, several passes of
+    # the analysis work group, a ragged last unit (1000 rings: 500 pairs)
+    "s2_k2_passes": (lambda: si.gauss_geometry(1000, 129, 0.1), 60, 60, 2, 1),
+    "s1_lmax_eq_s": (lambda: si.gauss_geometry(4, 9), 1, 1, 1, 1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPIN_CASES))
+def test_valu_spin_against_oracle_and_matrix_path(name):
+    sht = _sht()
+    build, lmax, mmax, spin, ntrans = SPIN_CASES[name]
+    g = build()
+    p = sht.Plan(sht.Geometry.from_inputs(g), lmax, mmax, spin=spin, ntrans=ntrans)
+    assert p.tuning()["valu"] == (1 if ntrans == 1 else 0), "the vector path is the default for one transform"
+    p.set_tuning(valu=1)
+    a = si.random_alm(lmax, mmax, ntrans, spin, tag=19 + spin)
+    d_a = to_dev(a)
+    mp = to_host(p.alm2map(d_a))
+    ref_map = oracle.synthesis(g, lmax, mmax, spin, a)
+    assert rel_err(mp, ref_map) < TOL64
+    back = to_host(p.map2alm(to_dev(ref_map)))
+    assert rel_err(back, oracle.analysis(g, lmax, mmax, spin, ref_map)) < TOL64
+    x = si.random_map(g, ntrans, 2, tag=23)
+    ref_t = oracle.adjoint_synthesis(g, lmax, mmax, spin, x)
+    assert rel_err(to_host(p.adjoint(to_dev(x))), ref_t) < TOL64
+    fac = np.where(si.lm_arrays(lmax, mmax)[1] == 0, 1.0, 2.0)[None, None, :, None]
+    assert rel_err(to_host(p.alm2map_grad(to_dev(x))), fac * ref_t) < TOL64
+    # the matrix-core kernels give the same sums up to rounding order
+    p.set_tuning(valu=0)
+    assert rel_err(to_host(p.alm2map(d_a)), mp) < 1e-13
+    assert rel_err(to_host(p.map2alm(to_dev(ref_map))), back) < 1e-13
+
+
+@pytest.mark.parametrize("geom,lmax,mmax,ntrans", [
+    (lambda: si.gauss_geometry(40, 81), 39, 25, 1),
+    (lambda: si.healpix_geometry(16), 40, 40, 2),
+    (lambda: si.ecp_geometry(33, 64, si.ECP_CC, 0.3), 30, 30, 1),
+], ids=["gl_mmax", "hp_j2", "cc_poles"])
+def test_valu_derivative_maps(geom, lmax, mmax, ntrans):
+    """Derivative maps on the vector kernels (E = sqrt(l (l + 1)) a, B = 0) and
+    their adjoint, against the oracle and the matrix-core kernels."""
+    sht = _sht()
+    g = geom()
+    p = sht.Plan(sht.Geometry.from_inputs(g), lmax, mmax, spin=1, ntrans=ntrans)
+    p.set_tuning(valu=1)
+    a = si.random_alm(lmax, mmax, ntrans, 0, tag=29)
+    d = to_host(p.alm2map_deriv1(to_dev(a)))
+    assert rel_err(d, oracle.deriv_synthesis(g, lmax, mmax, a)) < TOL64
+    x = si.random_map(g, ntrans, 2, tag=31)
+    ref = oracle.deriv_adjoint(g, lmax, mmax, x)
+    adj = to_host(p.deriv1_adjoint(to_dev(x)))
+    assert rel_err(adj, ref) < TOL64
+    fac = np.where(si.lm_arrays(lmax, mmax)[1] == 0, 1.0, 2.0)[None, None, :, None]
+    assert rel_err(to_host(p.alm2map_deriv1_grad(to_dev(x))), fac * ref) < TOL64
+    p.set_tuning(valu=0)
+    assert rel_err(to_host(p.alm2map_deriv1(to_dev(a))), d) < 1e-13
+    assert rel_err(to_host(p.deriv1_adjoint(to_dev(x))), adj) < 1e-13
+
+
 def test_valu_unsupported_combinations_rejected():
     sht = _sht()
     g = sht.Geometry.from_inputs(si.gauss_geometry(16, 31))
-    for kw in (dict(spin=2), dict(spin=0, precision="fp32_mfma")):
+    for kw in (dict(spin=0, precision="fp32_mfma"), dict(spin=2, precision="fp32_mfma")):
         p = sht.Plan(g, 15, ntrans=1, **kw)
         assert p.tuning()["valu"] == 0
         with pytest.raises(sht.ShtError) as e:
