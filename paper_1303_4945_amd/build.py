@@ -43,7 +43,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-o", tmp] + objs + DEVICE_FLAGS + ["-fPIC"]
+    # roctx: named ranges of the entry points for ROCm's tracing tools
+    cmd = [HIPCC, "-shared", "-o", tmp] + objs + DEVICE_FLAGS + ["-fPIC", "-L/opt/rocm/lib",
+                                                                 "-lrocprofiler-sdk-roctx"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "sht_internal.h"
+#include "trace.h"
 
 using namespace sht;
 
@@ -279,6 +280,7 @@ extern "C" {
 
 int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
 {
+    TraceRange tr("sht_batch_create");
     if (!out) { set_error("out is NULL"); return SHT_EINVAL; }
     *out = nullptr;
     if (nplans < 1 || !plans) { set_error("need at least one plan"); return SHT_EINVAL; }
@@ -344,7 +346,10 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
         delete b;
         return rc;
     }
-    reg_add(b, H_BATCH);
+    const uint64_t serial = reg_add(b, H_BATCH);
+    log_msg(1, "batch %llu created: %d plans, spin %d, %s, %d analysis queue items, %d persistent work groups",
+            (unsigned long long)serial, nplans, b->spin, b->precision == SHT_FP64 ? "fp64" : "fp32_mfma", b->nana,
+            b->ana_groups);
     *out = reinterpret_cast<sht_batch *>(b);
     return SHT_OK;
 }
@@ -380,10 +385,12 @@ int sht_batch_configure(sht_batch *h, int queue_order, int concurrent)
 int sht_batch_legendre(sht_batch *h, int direction, const double *const *in, double *const *out,
                        void *hip_stream)
 {
+    TraceRange tr("sht_batch_legendre");
     if (!reg_live(h, H_BATCH)) { set_error("invalid batch handle"); return SHT_ESTATE; }
     Batch *b = reinterpret_cast<Batch *>(h);
     int rc = check_batch_args(b, direction, in, out, true);
     if (rc) return rc;
+    log_msg(2, "sht_batch_legendre direction %d, %d plans, stream %p", direction, (int)b->plans.size(), hip_stream);
     hipStream_t s = (hipStream_t)hip_stream;
     const int np = (int)b->plans.size();
     if (synth_direction(direction)) {
@@ -403,10 +410,12 @@ int sht_batch_legendre(sht_batch *h, int direction, const double *const *in, dou
 int sht_batch_execute(sht_batch *h, int direction, const double *const *in, double *const *out,
                       void *hip_stream)
 {
+    TraceRange tr("sht_batch_execute");
     if (!reg_live(h, H_BATCH)) { set_error("invalid batch handle"); return SHT_ESTATE; }
     Batch *b = reinterpret_cast<Batch *>(h);
     int rc0 = check_batch_args(b, direction, in, out, false);
     if (rc0) return rc0;
+    log_msg(2, "sht_batch_execute direction %d, %d plans, stream %p", direction, (int)b->plans.size(), hip_stream);
     const int np = (int)b->plans.size();
     hipStream_t s = (hipStream_t)hip_stream;
     if (!s) {   // the null stream cannot be captured: plain launches
@@ -425,6 +434,7 @@ int sht_batch_execute(sht_batch *h, int direction, const double *const *in, doub
             (void)hipGraphExecDestroy(b->graph[direction]);
             b->graph[direction] = nullptr;
         }
+        log_msg(2, "batch: capturing direction %d into a graph", direction);
         int rc = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
         if (rc) return rc;
         rc = batch_enqueue(*b, direction, in, out, s);
@@ -450,6 +460,7 @@ void sht_batch_destroy(sht_batch *h)
 {
     if (!reg_live(h, H_BATCH)) return;
     Batch *b = reinterpret_cast<Batch *>(h);
+    log_msg(1, "batch destroyed (%d plans)", (int)b->plans.size());
     reg_remove(b);
     (void)hipDeviceSynchronize();
     batch_free(b);
@@ -458,13 +469,17 @@ void sht_batch_destroy(sht_batch *h)
 
 int sht_autotune(sht_plan *h, double budget_seconds)
 {
+    TraceRange tr("sht_autotune");
     Plan *p = plan_of(h);
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     if (!(budget_seconds >= 0.0)) { set_error("budget must be >= 0"); return SHT_EINVAL; }
     fault_arm();
     const std::string key = tune_key(*p);
     sht_tuning cached{};
-    if (tune_cache_lookup(key, cached) && tuning_check(*p, cached) == SHT_OK) return apply_tuning(*p, cached);
+    if (tune_cache_lookup(key, cached) && tuning_check(*p, cached) == SHT_OK) {
+        log_msg(1, "plan %llu: cached tuning %s", (unsigned long long)p->serial, tune_text(cached).c_str());
+        return apply_tuning(*p, cached);
+    }
     if (budget_seconds == 0.0) return SHT_OK;
 
     // candidates of each knob; the synthesis and the analysis knobs are
@@ -543,6 +558,7 @@ int sht_autotune(sht_plan *h, double budget_seconds)
     if (rc) return rc;
     if (rc2) return rc2;
     tune_cache_store(key, best);
+    log_msg(1, "plan %llu: autotuned %s", (unsigned long long)p->serial, tune_text(best).c_str());
     return SHT_OK;
 }
 

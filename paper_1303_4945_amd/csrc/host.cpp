@@ -27,6 +27,30 @@ void set_error(const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+    if (g_err[0]) log_msg(1, "error: %s", g_err);
+}
+
+int log_level()
+{
+    static const int level = [] {
+        const char *v = getenv("SHT_LOG");
+        const int n = v ? atoi(v) : 0;
+        return n < 0 ? 0 : (n > 3 ? 3 : n);
+    }();
+    return level;
+}
+
+void log_msg(int level, const char *fmt, ...)
+{
+    if (level > log_level()) return;
+    char line[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(line, sizeof(line), fmt, ap);
+    va_end(ap);
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    fprintf(stderr, "[sht:%d] %s\n", level, line);
 }
 
 // ------------------------------------------------------------------ registry
@@ -543,7 +567,9 @@ int sht_geom_create(int nrings, const double *theta, const int64_t *nphi, const 
             if (!std::isfinite(weight[i])) { set_error("weight[%d] not finite", i); return SHT_EINVAL; }
     Geom *g = geom_from(nrings, theta, nphi, phi0, weight, ofs, stride);
     if (!g) { set_error("host allocation failed"); return SHT_ENOMEM; }
-    reg_add(g, H_GEOM);
+    const uint64_t serial = reg_add(g, H_GEOM);
+    log_msg(1, "geometry %llu created: %d rings, %lld pixels, %s", (unsigned long long)serial, g->nrings,
+            (long long)g->npix, g->has_weight ? "ring weights" : "no ring weights");
     *out = reinterpret_cast<sht_geom *>(g);
     return SHT_OK;
 }
@@ -671,6 +697,7 @@ void sht_geom_destroy(sht_geom *g)
 {
     Geom *G = as_geom(g);
     if (!G) return;
+    log_msg(1, "geometry destroyed (%d rings)", G->nrings);
     reg_remove(G);
     delete G;
 }

@@ -15,6 +15,12 @@ namespace sht {
 
 void set_error(const char *fmt, ...);
 
+// Diagnostics on stderr, one line each, by the level in $SHT_LOG (read once):
+// 0 off (default), 1 handles created and destroyed, tuning choices and errors,
+// 2 also every entry-point call, 3 also every kernel launch with its grid.
+int log_level();
+void log_msg(int level, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
 // ---- registry of live handles --------------------------------------------
 // A handle is valid while it is registered; it is looked up before anything
 // is read through it, so a destroyed (or never created) handle is rejected

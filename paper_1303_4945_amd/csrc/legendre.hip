@@ -1973,6 +1973,9 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool 
 {
     if (p.synth_items.empty()) return SHT_OK;
     const LegView v = make_leg_view(p);
+    log_msg(3, "launch Legendre synthesis plan %llu: %zu items, %s kernels%s, stream %p",
+            (unsigned long long)p.serial, p.synth_items.size(), p.tune.valu ? "vector-unit" : "matrix-core",
+            deriv ? " (derivative maps)" : "", (void *)s);
     if (p.tune.valu && p.spin == 0) {
         if (valu_jpg(p) == 1) synth_valu_k<1>(p, v, alm, phase, s);
         else synth_valu_k<2>(p, v, alm, phase, s);
@@ -1996,6 +1999,9 @@ int launch_legendre_synth(const Plan &p, const double *alm, double *phase, bool 
 int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mode, hipStream_t s)
 {
     const LegView v = make_leg_view(p);
+    log_msg(3, "launch Legendre analysis plan %llu: %d m values x %d transforms, %s kernels, mode %d, stream %p",
+            (unsigned long long)p.serial, p.mmax + 1, p.ntrans, p.tune.valu ? "vector-unit" : "matrix-core", mode,
+            (void *)s);
     if (p.tune.valu && p.spin == 0) {
         if (valu_jpg(p) == 1) anal_valu_k<1>(p, v, phase, alm, mode, s);
         else anal_valu_k<2>(p, v, phase, alm, mode, s);
@@ -2061,6 +2067,8 @@ static void launch_anal_batch_t(const Batch &b, const BatchPtrs &ptrs, int mode,
 int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s)
 {
     if (b.nana == 0) return SHT_OK;
+    log_msg(3, "launch persistent batch Legendre analysis: %d items, %d work groups, mode %d, stream %p", b.nana,
+            b.ana_groups, mode, (void *)s);
     const bool f32 = b.precision == SHT_FP32_MFMA;
     const int key = (b.spin ? 4 : 0) + (b.ana_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
     switch (key) {

@@ -17,6 +17,7 @@
 #include <unordered_map>
 
 #include "sht_internal.h"
+#include "trace.h"
 
 namespace sht {
 
@@ -71,10 +72,13 @@ extern "C" {
 
 int sht_execute_noalloc(sht_plan *h, int direction, const double *in, double *out, void *hip_stream)
 {
+    TraceRange tr("sht_execute_noalloc");
     Plan *p = plan_of(h);
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     int rc = check_exec_args(p, direction, in, out, false, false);
     if (rc) return rc;
+    log_msg(2, "sht_execute_noalloc plan %llu direction %d stream %p", (unsigned long long)p->serial, direction,
+            hip_stream);
     size_t rh_ofs = 0;
     const size_t need = exec_workspace_bytes(*p, &rh_ofs);
     if (need > SCRATCH_BYTES) {

@@ -1638,6 +1638,8 @@ int launch_ring_synth(const Plan &p, const double *phase, double *map, bool use_
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
         const hipStream_t s = group_stream(*D, i, s0, conc);
+        log_msg(3, "launch ring FFT (%s) plan %llu: group %zu, mode %d, %zu rows x %d, LDS %d complex, stream %p",
+                "synthesis", (unsigned long long)p.serial, i, gr.mode, gr.rows.size(), ntc, gr.lds_complex, (void *)s);
         int rc;
         // split Bluestein always has a power-of-two inner length
         if (gr.mode == KMODE_SPLIT) rc = launch_group_synth<KMODE_SPLIT, true>(v, gr, rows, phase, map, ntc, usew, s);
@@ -1664,6 +1666,8 @@ int launch_ring_anal(const Plan &p, const double *map, double *phase, bool use_w
         const FftGroup &gr = D->groups[i];
         const int *rows = D->group_rows[i];
         const hipStream_t s = group_stream(*D, i, s0, conc);
+        log_msg(3, "launch ring FFT (%s) plan %llu: group %zu, mode %d, %zu rows x %d, LDS %d complex, stream %p",
+                "analysis", (unsigned long long)p.serial, i, gr.mode, gr.rows.size(), ntc, gr.lds_complex, (void *)s);
         int rc;
         if (gr.mode == KMODE_SPLIT) rc = launch_group_anal<KMODE_SPLIT, true>(v, gr, rows, map, phase, ntc, uw, s);
         else if (gr.mode == KMODE_RADER && gr.pow2) rc = launch_group_anal<KMODE_RADER, true>(v, gr, rows, map, phase, ntc, uw, s);

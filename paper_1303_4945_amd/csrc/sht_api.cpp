@@ -16,6 +16,7 @@
 #include <unordered_map>
 
 #include "sht_internal.h"
+#include "trace.h"
 
 namespace sht {
 
@@ -391,6 +392,7 @@ extern "C" {
 int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans, int precision,
                     const sht_plan_opts *opts, sht_plan **out)
 {
+    TraceRange tr("sht_plan_create");
     if (!out) { set_error("out is NULL"); return SHT_EINVAL; }
     *out = nullptr;
     const Geom *G = geom_of(g);
@@ -442,6 +444,12 @@ int sht_plan_create(const sht_geom *g, int lmax, int mmax, int spin, int ntrans,
         return rc;
     }
     p->serial = reg_add(p, H_PLAN);
+    log_msg(1,
+            "plan %llu created on device %d: lmax %d, mmax %d, spin %d, %d transforms, %s, %d slots in %d tiles, "
+            "%lld synthesis items; tuning synth_ncb=%d synth_mblock=%d anal_ncb=%d anal_tpw=%d valu=%d",
+            (unsigned long long)p->serial, dev, lmax, mmax, spin, ntrans, precision == SHT_FP64 ? "fp64" : "fp32_mfma",
+            p->nslots, p->ntiles, (long long)p->n_items, p->tune.synth_ncb, p->tune.synth_mblock, p->tune.anal_ncb,
+            p->tune.anal_tpw, p->tune.valu);
     *out = reinterpret_cast<sht_plan *>(p);
     return SHT_OK;
 }
@@ -450,6 +458,7 @@ void sht_plan_destroy(sht_plan *h)
 {
     Plan *p = as_plan(h);
     if (!p) return;
+    log_msg(1, "plan %llu destroyed", (unsigned long long)p->serial);
     reg_remove(p);
     (void)hipDeviceSynchronize();
     plan_free_device(p);
@@ -458,19 +467,23 @@ void sht_plan_destroy(sht_plan *h)
 
 int sht_execute(sht_plan *h, int direction, const double *in, double *out, void *hip_stream)
 {
+    TraceRange tr("sht_execute");
     Plan *p = as_plan(h);
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     int rc = check_exec_args(p, direction, in, out, false, false);
     if (rc) return rc;
+    log_msg(2, "sht_execute plan %llu direction %d stream %p", (unsigned long long)p->serial, direction, hip_stream);
     return execute_with(*p, direction, in, out, p->d_phase, p->d_rh, (hipStream_t)hip_stream);
 }
 
 int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void *hip_stream)
 {
+    TraceRange tr("sht_legendre");
     Plan *p = as_plan(h);
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     int rc = check_exec_args(p, direction, in, out, false, true);
     if (rc) return rc;
+    log_msg(2, "sht_legendre plan %llu direction %d stream %p", (unsigned long long)p->serial, direction, hip_stream);
     hipStream_t s = (hipStream_t)hip_stream;
     const int acomp = deriv_direction(direction) ? 1 : p->ncomp;
     if (synth_direction(direction)) {
@@ -491,10 +504,12 @@ int sht_legendre(sht_plan *h, int direction, const double *in, double *out, void
 
 int sht_ring_fft(sht_plan *h, int direction, const double *in, double *out, void *hip_stream)
 {
+    TraceRange tr("sht_ring_fft");
     Plan *p = as_plan(h);
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     int rc = check_exec_args(p, direction, in, out, true, false);
     if (rc) return rc;
+    log_msg(2, "sht_ring_fft plan %llu direction %d stream %p", (unsigned long long)p->serial, direction, hip_stream);
     hipStream_t s = (hipStream_t)hip_stream;
     if (synth_direction(direction)) {
         rc = launch_ring_synth(*p, in, out, weighted_direction(direction), s);
@@ -521,7 +536,11 @@ int sht_plan_set_tuning(sht_plan *h, const sht_tuning *t)
     if (!p) { set_error("invalid plan handle"); return SHT_ESTATE; }
     if (!t) { set_error("t is NULL"); return SHT_EINVAL; }
     fault_arm();
-    return apply_tuning(*p, *t);
+    const int rc = apply_tuning(*p, *t);
+    if (!rc)
+        log_msg(1, "plan %llu tuning set: synth_ncb=%d synth_mblock=%d anal_ncb=%d anal_tpw=%d valu=%d",
+                (unsigned long long)p->serial, t->synth_ncb, t->synth_mblock, t->anal_ncb, t->anal_tpw, t->valu);
+    return rc;
 }
 
 int sht_plan_flops(const sht_plan *h, int direction, double *flops_fp64, double *flops_mfma,
