@@ -1905,7 +1905,9 @@ int valu_jpg(const Plan &p) { return (p.spin == 0 && p.ntrans >= 2) ? 2 : 1; }
 // analysis 1.43 ms with four, 1.49 with two)
 int valu_k(const Plan &p, bool anal)
 {
-    const int kmax = (anal && p.spin == 0 && valu_jpg(p) == 1) ? 4 : 2;
+    // analysis, spin 0: four slots per lane (registers 208 for one transform,
+    // 239 for two; six would leave one wavefront per SIMD); otherwise two
+    const int kmax = (anal && p.spin == 0) ? 4 : 2;
     const int units = (p.nslots + 63) / 64;   // 64-slot units (spin plans: two tiles each)
     const int k = units >= 8 ? 4 : (units >= 2 ? 2 : 1);
     return k < kmax ? k : kmax;
@@ -1963,7 +1965,7 @@ template <int J>
 static void anal_valu_k(const Plan &p, const LegView &v, const double *phase, double *alm, int mode, hipStream_t s)
 {
     switch (valu_k(p, true)) {
-    case 4: launch_anal_valu_t<J, (J == 1 ? 4 : 2)>(p, v, phase, alm, mode, s); break;
+    case 4: launch_anal_valu_t<J, 4>(p, v, phase, alm, mode, s); break;
     case 2: launch_anal_valu_t<J, 2>(p, v, phase, alm, mode, s); break;
     default: launch_anal_valu_t<J, 1>(p, v, phase, alm, mode, s); break;
     }

@@ -27,11 +27,12 @@ CASES = {
     "hp_j3_ragged": (lambda: si.healpix_geometry(8), 23, 23, 3),   # groups of two, the last one ragged
     "gl_lmax0": (lambda: si.gauss_geometry(1, 1), 0, 0, 1),
     "gl_j1_long": (lambda: si.gauss_geometry(200, 399), 199, 199, 1),
-    # many rings at a small lmax: two slots per lane in the synthesis, four
-    # (one transform) or two (two transforms) in the analysis, tiles of several
+    # many rings at a small lmax: two slots per lane in the synthesis, four in
+    # the analysis (two with fewer than eight 64-slot units), tiles of several
     # passes of the analysis work group, most polar tiles skipped at the higher m
     "gl_j1_k4": (lambda: si.gauss_geometry(1000, 129, 0.1), 60, 60, 1),
-    "gl_j2_k2": (lambda: si.gauss_geometry(1000, 129), 60, 45, 2),
+    "gl_j2_k4": (lambda: si.gauss_geometry(1000, 129), 60, 45, 2),
+    "gl_j2_k2": (lambda: si.gauss_geometry(300, 129), 60, 60, 2),   # 150 slots: three 64-slot units
     "gl_j1_k4_passes": (lambda: si.gauss_geometry(2100, 67), 33, 33, 1),
 }
 
