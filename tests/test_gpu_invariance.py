@@ -181,6 +181,41 @@ def test_gl4095_spin2_workload_sampled():
     assert pd_or[2:].max() < PER_DEGREE_LOW_M_FP32
 
 
+def test_gl4095_spin2_single_transform_vector_path_sampled():
+    """One spin-2 transform at the full Gauss-Legendre 4096 x 8191, lmax 4095
+    size: the plan takes the vector-unit Legendre kernels by default (the
+    single-transform leg of the benchmark); sampled rings and m values against
+    the oracle to 1e-11, the exact round trip, and the matrix-core kernels of
+    the same plan equal to rounding, per degree at the top of the spectrum."""
+    sht = _sht()
+    lmax = 4095
+    g = si.gauss_geometry(4096, 8191)
+    geom = sht.Geometry.from_inputs(g)
+    a = si.random_alm(lmax, lmax, 1, 2, tag=77)
+    d_a = to_dev(a)
+    p = sht.Plan(geom, lmax, spin=2, ntrans=1)
+    assert p.tuning()["valu"] == 1
+    mp_h = to_host(p.alm2map(d_a))
+    back = to_host(p.map2alm(to_dev(mp_h)))
+    rings = np.array([0, 1, 700, 2047, 2048, 4094, 4095])
+    ms = np.array([0, 1, 2, 3, 2000, 4094, 4095])
+    ref_map = oracle.synthesis(g, lmax, lmax, 2, a, rings=rings)
+    pix = np.concatenate([np.arange(g.ofs[y], g.ofs[y] + g.nphi[y]) for y in rings])
+    assert rel_err(mp_h[..., pix], ref_map[..., pix]) < TOL64
+    ref_alm = oracle.analysis(g, lmax, lmax, 2, mp_h, ms=ms)
+    sel = np.concatenate([np.arange(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+                          for m in ms])
+    assert rel_err(back[:, :, sel], ref_alm[:, :, sel]) < TOL64
+    assert rel_err(back, a) < 1e-10
+    p.set_tuning(valu=0)
+    back_m = to_host(p.map2alm(to_dev(mp_h)))
+    assert rel_err(back, back_m) < 1e-13
+    # per degree, each against its own power over all m (l < 2: no spin-2 terms)
+    pd = _per_degree_rel(back, back_m, lmax)
+    print(f"\nvector vs matrix-core analysis, per-degree max {pd[2:].max():.2e} at l = {2 + int(np.argmax(pd[2:]))}")
+    assert pd[2:].max() < 1e-12
+
+
 def test_healpix1024_workload_sampled():
     """HEALPix N_side = 1024 (4095 rings), lmax 2047, one scalar transform."""
     sht = _sht()
