@@ -470,7 +470,8 @@ def run_mixed(args):
     """Batching form: 64 scalar transforms (16 each at lmax 255/511/1023/2047,
     GL grids of lmax+1 rings x 2lmax+1 px) as one batch on a non-default stream
     (captured into a HIP graph), against the four plans run one after another;
-    each schedule of the batch (queue order, concurrent plan chains) is timed,
+    each schedule of the batch (queue order; per-plan chains on one stream or
+    concurrent streams, or the persistent synthesis over all plans) is timed,
     the fastest is the reported value.  The staged batch Legendre steps are
     timed with events for the roofline of the persistent analysis kernel."""
     import torch
@@ -517,16 +518,24 @@ def run_mixed(args):
     res = {}
     with torch.cuda.stream(s):
         res["plans_one_by_one"] = timed(plans_step, args.steps)
-        for order, conc in ((sht.QUEUE_COST, True), (sht.QUEUE_MPAIRS, True), (sht.QUEUE_COST, False),
-                            (sht.QUEUE_MPAIRS, False)):
-            b.configure(order, conc)
-            name = f"batch_{'cost' if order == sht.QUEUE_COST else 'mpairs'}_{'concurrent' if conc else 'serial'}"
-            res[name] = timed(batch_step, args.steps)
+        sched = {"serial": 0, "concurrent": 1, "persistent_synthesis": 2}
+        for conc in ("concurrent", "serial", "persistent_synthesis"):
+            for order in (sht.QUEUE_COST, sht.QUEUE_MPAIRS):
+                b.configure(order, sched[conc])
+                name = f"batch_{'cost' if order == sht.QUEUE_COST else 'mpairs'}_{conc}"
+                res[name] = timed(batch_step, args.steps)
         best = min((k for k in res if k.startswith("batch")), key=lambda k: res[k])
-        b.configure(sht.QUEUE_MPAIRS if "mpairs" in best else sht.QUEUE_COST, "concurrent" in best)
+        b.configure(sht.QUEUE_MPAIRS if "mpairs" in best else sht.QUEUE_COST,
+                    next(v for k, v in sched.items() if best.endswith(k)))
+        # staged Legendre synthesis as one persistent launch over all plans
+        b.configure(sht.QUEUE_COST, 2)
+        leg_persistent = timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps)
+        b.configure(sht.QUEUE_MPAIRS if "mpairs" in best else sht.QUEUE_COST,
+                    next(v for k, v in sched.items() if best.endswith(k)))
         ms = timed(batch_step, args.steps)
         # staged Legendre steps of the batch (events on the launch stream)
-        leg = {"legendre_synth": timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps)}
+        leg = {"legendre_synth": timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps),
+               "legendre_synth_persistent": leg_persistent}
         b.legendre(sht.ALM2MAP, alms, ph, stream=s)
         leg["legendre_anal"] = timed(lambda: b.legendre(sht.MAP2ALM, ph, back, stream=s), args.steps)
     log(f"mixed: {res}; chosen {best}: {ms:.2f} ms/pair-step; staged Legendre {leg}")

@@ -279,8 +279,14 @@ int sht_batch_legendre(sht_batch *b, int direction, const double *const *in,
    concurrent   1: every plan's launch chain (synthesis: Legendre step then
                 ring FFTs; analysis: ring FFTs) runs on a stream of its own
                 between a fork and a join on the caller's stream, so that small
-                plans fill the gaps of large ones; 0: one stream.
-   Defaults: SHT_QUEUE_COST, concurrent 1.  Results do not depend on either. */
+                plans fill the gaps of large ones; 0: one stream; 2: as 1 for
+                the ring FFTs, while the Legendre syntheses of all plans run as
+                one persistent launch over one queue of (plan, m, slot tile,
+                transform group) items in the queue order (needs every plan on
+                the matrix-core kernels with the same synthesis column blocks
+                and carry interval, else the plans' own launches run).
+   Defaults: SHT_QUEUE_COST, concurrent 1.  Results do not depend on either.
+   SHT_EINVAL for other values. */
 enum { SHT_QUEUE_COST = 0, SHT_QUEUE_MPAIRS = 1 };
 int sht_batch_configure(sht_batch *b, int queue_order, int concurrent);
 

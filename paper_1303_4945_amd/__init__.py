@@ -410,8 +410,12 @@ class Batch:
         _check(_lib.sht_batch_execute(self._h, direction, a_in, a_out, _stream_handle(stream)))
         return outs
 
-    def configure(self, queue_order: int = QUEUE_COST, concurrent: bool = True):
-        _check(_lib.sht_batch_configure(self._h, int(queue_order), 1 if concurrent else 0))
+    def configure(self, queue_order: int = QUEUE_COST, concurrent=True):
+        """Queue order and schedule: concurrent True/1 (per-plan chains on
+        their own streams), False/0 (one stream) or 2 (persistent synthesis
+        over all plans, then per-plan ring FFTs on their own streams)."""
+        c = int(concurrent) if not isinstance(concurrent, bool) else (1 if concurrent else 0)
+        _check(_lib.sht_batch_configure(self._h, int(queue_order), c))
 
     def legendre(self, direction, ins, outs, stream=None):
         """Legendre step only of every plan (phases <-> coefficients)."""

@@ -29,6 +29,7 @@ void batch_free(Batch *b)
     b->join.clear();
     dev_free(b->d_views);
     dev_free(b->d_ana);
+    dev_free(b->d_syn);
     dev_free(b->d_counter);
 }
 
@@ -67,6 +68,83 @@ void anal_queue(const Batch &b, std::vector<BatchAnaItem> &q)
     q.clear();
     for (auto &e : v) q.push_back(e.second);
 }
+
+// Queue of synthesis items of all plans (persistent synthesis): one item per
+// (plan, m, slot tile active at m, transform group of the plan's column
+// blocks); SHT_QUEUE_COST: by decreasing degree range; SHT_QUEUE_MPAIRS: the
+// same tile and group at m and mmax - m in one item, by decreasing pair cost.
+void synth_queue(const Batch &b, std::vector<BatchSynItem> &q)
+{
+    const int cpj = b.spin ? 4 : 2;
+    std::vector<std::pair<double, BatchSynItem>> v;
+    for (int pi = 0; pi < (int)b.plans.size(); ++pi) {
+        const Plan &p = *b.plans[pi];
+        const int jpg = p.tune.synth_ncb * 16 / cpj;
+        auto lrange = [&](int m) { return (double)(p.lmax + 1 - std::max(m, p.spin)); };
+        if (b.queue_order == SHT_QUEUE_MPAIRS) {
+            for (int m = 0; m <= p.mmax - m; ++m) {
+                const int m2 = p.mmax - m;
+                for (int t = 0; t < p.ntiles; ++t) {
+                    const bool a1 = p.tile_mlim[t] >= m, a2 = m2 != m && p.tile_mlim[t] >= m2;
+                    if (!a1 && !a2) continue;
+                    const double c = (a1 ? lrange(m) : 0.0) + (a2 ? lrange(m2) : 0.0);
+                    for (int t0 = 0; t0 < p.ntrans; t0 += jpg)
+                        v.push_back({c, BatchSynItem{pi, a1 ? m : m2, (a1 && a2) ? m2 : -1, t, t0, {0, 0, 0}}});
+                }
+            }
+        } else {
+            for (int m = 0; m <= p.mmax; ++m)
+                for (int t = 0; t < p.ntiles; ++t) {
+                    if (p.tile_mlim[t] < m) continue;
+                    for (int t0 = 0; t0 < p.ntrans; t0 += jpg)
+                        v.push_back({lrange(m), BatchSynItem{pi, m, -1, t, t0, {0, 0, 0}}});
+                }
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
+    q.clear();
+    for (auto &e : v) q.push_back(e.second);
+}
+
+// (Re)builds the synthesis queue when the plans' work lists changed since it
+// was built, or when forced (new queue order).  Host work, a device
+// synchronization (the old queue may still be read) and an upload: refused
+// while the stream s is being captured.
+int refresh_synth_queue(Batch &b, hipStream_t s, bool force)
+{
+    std::vector<uint64_t> gen;
+    for (const Plan *p : b.plans) gen.push_back(p->generation);
+    if (!force && gen == b.syn_gen) return SHT_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        set_error("a plan of the batch was retuned: run the batch once outside stream capture first");
+        return SHT_ESTATE;
+    }
+    if (b.d_syn) (void)hipDeviceSynchronize();
+    const Plan &p0 = *b.plans[0];
+    b.syn_ok = true;
+    for (const Plan *p : b.plans)
+        if (p->tune.valu || p->tune.synth_ncb != p0.tune.synth_ncb || p->flush_chunks != p0.flush_chunks)
+            b.syn_ok = false;
+    dev_free(b.d_syn);
+    b.d_syn = nullptr;
+    b.nsyn = 0;
+    b.syn_gen = gen;
+    if (!b.syn_ok) return SHT_OK;
+    b.syn_ncb = p0.tune.synth_ncb;
+    b.syn_flush = p0.flush_chunks;
+    b.syn_groups = synth_batch_groups(b.spin, b.syn_ncb, b.precision == SHT_FP32_MFMA, b.device);
+    std::vector<BatchSynItem> q;
+    synth_queue(b, q);
+    int rc;
+    if ((rc = dev_alloc((void **)&b.d_syn, std::max<size_t>(1, q.size()) * sizeof(BatchSynItem), "batch tables")))
+        return rc;
+    b.nsyn = (int)q.size();
+    if (!q.empty()) return dev_upload(b.d_syn, q.data(), q.size() * sizeof(BatchSynItem), "batch tables");
+    return SHT_OK;
+}
+
+bool persistent_synth(const Batch &b) { return b.concurrent == 2 && b.syn_ok; }
 
 int upload_queue(Batch &b)
 {
@@ -150,11 +228,43 @@ int batch_legendre_anal(Batch &b, int direction, const double *const *phase, dou
     return SHT_OK;
 }
 
+// Persistent Legendre synthesis of all plans on s into phase[i] (with the
+// real-harmonics conversions first).
+int batch_legendre_synth(Batch &b, int direction, const double *const *in, double *const *phase, hipStream_t s)
+{
+    BatchPtrs ptrs;
+    std::memset(&ptrs, 0, sizeof(ptrs));
+    int rc;
+    for (int i = 0; i < (int)b.plans.size(); ++i) {
+        Plan &p = *b.plans[i];
+        ptrs.in[i] = in[i];
+        ptrs.out[i] = phase[i];
+        if (b.real_h) {
+            if ((rc = launch_real_harm(p, in[i], p.d_rh, deriv_direction(direction) ? 1 : p.ncomp, true, s))) return rc;
+            ptrs.in[i] = p.d_rh;
+        }
+    }
+    return launch_legendre_synth_batch(b, ptrs, deriv_direction(direction), s);
+}
+
 // Everything one execution of the batch puts on the stream.
 int batch_enqueue(Batch &b, int direction, const double *const *in, double *const *out, hipStream_t s)
 {
     const int np = (int)b.plans.size();
     int rc;
+    if (synth_direction(direction) && persistent_synth(b)) {
+        // one persistent Legendre launch over all plans, then every plan's ring
+        // FFTs on its own stream
+        std::vector<double *> ph(np);
+        for (int i = 0; i < np; ++i) ph[i] = b.plans[i]->d_phase;
+        if ((rc = batch_legendre_synth(b, direction, in, ph.data(), s))) return rc;
+        if ((rc = fork_chains(b, s))) return rc;
+        for (int i = 0; i < np; ++i)
+            if ((rc = launch_ring_synth(*b.plans[i], b.plans[i]->d_phase, out[i], weighted_direction(direction),
+                                        chain_stream(b, i, s))))
+                return rc;
+        return join_chains(b, s);
+    }
     if ((rc = fork_chains(b, s))) return rc;
     if (synth_direction(direction)) {
         // per plan: its die-aware Legendre item list, then its ring FFTs
@@ -326,7 +436,8 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
     int rc;
     if ((rc = dev_alloc((void **)&b->d_views, views.size() * sizeof(LegView), "batch tables")) ||
         (rc = dev_upload(b->d_views, views.data(), views.size() * sizeof(LegView), "batch tables")) ||
-        (rc = upload_queue(*b)) || (rc = dev_alloc((void **)&b->d_counter, 64, "batch counter"))) {
+        (rc = upload_queue(*b)) || (rc = refresh_synth_queue(*b, nullptr, true)) ||
+        (rc = dev_alloc((void **)&b->d_counter, 128, "batch counter"))) {
         batch_free(b);
         delete b;
         return rc;
@@ -362,18 +473,23 @@ int sht_batch_configure(sht_batch *h, int queue_order, int concurrent)
         set_error("unknown queue order %d", queue_order);
         return SHT_EINVAL;
     }
-    if (concurrent != 0 && concurrent != 1) { set_error("concurrent must be 0 or 1"); return SHT_EINVAL; }
+    if (concurrent < 0 || concurrent > 2) { set_error("concurrent must be 0, 1 or 2"); return SHT_EINVAL; }
     (void)hipDeviceSynchronize();
     fault_arm();
     const int old_order = b->queue_order;
     b->queue_order = queue_order;
     b->concurrent = concurrent;
     int rc = upload_queue(*b);
+    if (!rc) rc = refresh_synth_queue(*b, nullptr, true);
     if (rc) {
         b->queue_order = old_order;
         (void)upload_queue(*b);
+        (void)refresh_synth_queue(*b, nullptr, true);
         return rc;
     }
+    if (concurrent == 2 && !b->syn_ok)
+        log_msg(1, "batch: persistent synthesis needs every plan on the matrix-core path with one shape; "
+                   "per-plan synthesis launches instead");
     for (int d = 0; d < NUM_DIRECTIONS; ++d)
         if (b->graph[d]) {
             (void)hipGraphExecDestroy(b->graph[d]);
@@ -393,7 +509,12 @@ int sht_batch_legendre(sht_batch *h, int direction, const double *const *in, dou
     log_msg(2, "sht_batch_legendre direction %d, %d plans, stream %p", direction, (int)b->plans.size(), hip_stream);
     hipStream_t s = (hipStream_t)hip_stream;
     const int np = (int)b->plans.size();
-    if (synth_direction(direction)) {
+    if ((rc = refresh_synth_queue(*b, s, false))) return rc;
+    if (synth_direction(direction) && persistent_synth(*b)) {
+        if ((rc = batch_legendre_synth(*b, direction, in, out, s))) return rc;
+        for (int i = 0; i < np; ++i)
+            if ((rc = launch_phase_tail_zero(*b->plans[i], out[i], s))) return rc;
+    } else if (synth_direction(direction)) {
         if ((rc = fork_chains(*b, s))) return rc;
         for (int i = 0; i < np; ++i) {
             const hipStream_t cs = chain_stream(*b, i, s);
@@ -415,6 +536,7 @@ int sht_batch_execute(sht_batch *h, int direction, const double *const *in, doub
     Batch *b = reinterpret_cast<Batch *>(h);
     int rc0 = check_batch_args(b, direction, in, out, false);
     if (rc0) return rc0;
+    if ((rc0 = refresh_synth_queue(*b, (hipStream_t)hip_stream, false))) return rc0;
     log_msg(2, "sht_batch_execute direction %d, %d plans, stream %p", direction, (int)b->plans.size(), hip_stream);
     const int np = (int)b->plans.size();
     hipStream_t s = (hipStream_t)hip_stream;

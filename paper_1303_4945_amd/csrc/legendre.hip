@@ -962,6 +962,33 @@ __global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_ana
     }
 }
 
+// Persistent synthesis for a batch of plans: every wavefront takes items from
+// one queue (atomic counter) until it is empty; all lanes read the same index,
+// so the whole wavefront leaves together.
+template <int SPIN, int NCB, bool F32>
+__global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__restrict__ views,
+                                                             const BatchSynItem *__restrict__ items, int nitems,
+                                                             BatchPtrs ptrs, int flush_chunks, int deriv,
+                                                             unsigned *counter)
+{
+    __shared__ SynShared<SPIN, F32> sh;
+    for (;;) {
+        unsigned got = 0;
+        if (threadIdx.x == 0) got = atomicAdd(counter, 1u);
+        const unsigned idx = __builtin_amdgcn_readfirstlane(got);   // lane 0's value
+        if (idx >= (unsigned)nitems) break;
+        const BatchSynItem bi = items[idx];
+        synth_item<SPIN, NCB, F32>(views[bi.plan], WaveItem{bi.m, bi.tile, bi.t0, 0}, ptrs.in[bi.plan],
+                                   ptrs.out[bi.plan], flush_chunks, deriv, sh);
+        __syncthreads();   // this item's LDS reads are done before the next item's writes
+        if (bi.m2 >= 0) {
+            synth_item<SPIN, NCB, F32>(views[bi.plan], WaveItem{bi.m2, bi.tile, bi.t0, 0}, ptrs.in[bi.plan],
+                                       ptrs.out[bi.plan], flush_chunks, deriv, sh);
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- vector path
 //
 // For a few simultaneous spin-0 transforms most matrix-core columns would be
@@ -2055,6 +2082,57 @@ int anal_batch_groups(int spin, int ncb, bool f32, int dev)
     case 6: return anal_batch_groups_t<2, 2, false>(dev);
     default: return anal_batch_groups_t<2, 2, true>(dev);
     }
+}
+
+template <int SPIN, int NCB, bool F32>
+static int synth_batch_groups_t(int dev)
+{
+    return persistent_groups(k_legendre_synth_batch<SPIN, NCB, F32>, 64, dev);
+}
+
+int synth_batch_groups(int spin, int ncb, bool f32, int dev)
+{
+    const int key = (spin ? 4 : 0) + (ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
+    switch (key) {
+    case 0: return synth_batch_groups_t<0, 1, false>(dev);
+    case 1: return synth_batch_groups_t<0, 1, true>(dev);
+    case 2: return synth_batch_groups_t<0, 2, false>(dev);
+    case 3: return synth_batch_groups_t<0, 2, true>(dev);
+    case 4: return synth_batch_groups_t<2, 1, false>(dev);
+    case 5: return synth_batch_groups_t<2, 1, true>(dev);
+    case 6: return synth_batch_groups_t<2, 2, false>(dev);
+    default: return synth_batch_groups_t<2, 2, true>(dev);
+    }
+}
+
+template <int SPIN, int NCB, bool F32>
+static void launch_synth_batch_t(const Batch &b, const BatchPtrs &ptrs, int deriv, hipStream_t s)
+{
+    unsigned *counter = b.d_counter + 16;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    hipLaunchKernelGGL((k_legendre_synth_batch<SPIN, NCB, F32>), dim3((unsigned)b.syn_groups), dim3(64), 0, s,
+                       b.d_views, b.d_syn, b.nsyn, ptrs, b.syn_flush, deriv, counter);
+}
+
+int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s)
+{
+    if (b.nsyn == 0) return SHT_OK;
+    log_msg(3, "launch persistent batch Legendre synthesis: %d items, %d wavefronts%s, stream %p", b.nsyn,
+            b.syn_groups, deriv ? " (derivative maps)" : "", (void *)s);
+    const bool f32 = b.precision == SHT_FP32_MFMA;
+    const int d = deriv ? 1 : 0;
+    const int key = (b.spin ? 4 : 0) + (b.syn_ncb == 2 ? 2 : 0) + (f32 ? 1 : 0);
+    switch (key) {
+    case 0: launch_synth_batch_t<0, 1, false>(b, ptrs, 0, s); break;
+    case 1: launch_synth_batch_t<0, 1, true>(b, ptrs, 0, s); break;
+    case 2: launch_synth_batch_t<0, 2, false>(b, ptrs, 0, s); break;
+    case 3: launch_synth_batch_t<0, 2, true>(b, ptrs, 0, s); break;
+    case 4: launch_synth_batch_t<2, 1, false>(b, ptrs, d, s); break;
+    case 5: launch_synth_batch_t<2, 1, true>(b, ptrs, d, s); break;
+    case 6: launch_synth_batch_t<2, 2, false>(b, ptrs, d, s); break;
+    default: launch_synth_batch_t<2, 2, true>(b, ptrs, d, s); break;
+    }
+    return check_hip(hipGetLastError(), "batch legendre synthesis launch");
 }
 
 template <int SPIN, int NCB, bool F32>

@@ -39,6 +39,18 @@ struct BatchAnaItem {
     int m2;   // second m of the item (-1: none)
 };
 
+// Items of the persistent batch synthesis kernel: one wavefront's (m, slot
+// tile, transform group) of one plan, or (queue of m pairs) the same tile and
+// group at m and then at m2 = mmax - m (-1: none).
+struct BatchSynItem {
+    int plan;
+    int m;
+    int m2;
+    int tile;
+    int t0;
+    int pad[3];
+};
+
 // Device-side view of one plan for the Legendre kernels.
 struct LegView {
     int lmax, mmax, spin, ntrans, nrings, nslots, ntiles;
@@ -151,7 +163,14 @@ struct Batch {
     int nana = 0;
     LegView *d_views = nullptr;
     BatchAnaItem *d_ana = nullptr;
-    unsigned *d_counter = nullptr;
+    unsigned *d_counter = nullptr;       // [0]: analysis queue, [16]: synthesis queue
+    // persistent synthesis (concurrent == 2): one queue over all plans, built
+    // for the plans' tunings at the generations in syn_gen; syn_ok: every plan
+    // on the matrix-core path with the same column blocks and carry interval
+    bool syn_ok = false;
+    int nsyn = 0, syn_groups = 1, syn_ncb = 1, syn_flush = 4;
+    BatchSynItem *d_syn = nullptr;
+    std::vector<uint64_t> syn_gen;
     // captured graphs, one per direction, keyed by the user pointers and the
     // plans' generations (a retuned plan has new item lists and launch shapes)
     hipGraphExec_t graph[NUM_DIRECTIONS] = {};
@@ -177,6 +196,9 @@ int launch_legendre_anal(const Plan &p, const double *phase, double *alm, int mo
 
 // persistent batch launchers (legendre.hip); pointer tables already staged in b.d_ptr
 int launch_legendre_anal_batch(const Batch &b, const BatchPtrs &ptrs, int mode, hipStream_t s);
+int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s);
+// work groups (one wavefront each) of the persistent synthesis launch on the given device
+int synth_batch_groups(int spin, int ncb, bool f32, int device);
 // work groups of the persistent analysis launch on the given device
 int anal_batch_groups(int spin, int ncb, bool f32, int device);
 int anal_ncb(int spin, int ntrans);

@@ -254,11 +254,12 @@ def test_autotune_keeps_results_and_writes_cache(tmp_path):
         del os.environ["SHT_TUNE_CACHE"]
 
 
-@pytest.mark.parametrize("order,concurrent", [(1, 1), (0, 0), (1, 0)])
+@pytest.mark.parametrize("order,concurrent", [(1, 1), (0, 0), (1, 0), (0, 2), (1, 2)])
 def test_batch_schedules_give_identical_results(order, concurrent):
-    """Queue of (m, mmax - m) pairs and/or one stream for all plans: the same
-    results bit for bit as the plans' own launches, eager and graph-replayed;
-    the staged batch Legendre step equals the plans' staged steps."""
+    """Queue of (m, mmax - m) pairs, one stream for all plans, or the persistent
+    synthesis over all plans (concurrent 2): the same results bit for bit as the
+    plans' own launches, eager and graph-replayed; the staged batch Legendre
+    step equals the plans' staged steps."""
     import ctypes
     import torch
     sht = _sht()
@@ -291,3 +292,65 @@ def test_batch_schedules_give_identical_results(order, concurrent):
     for p, f, o in zip(plans, F, out):
         assert np.array_equal(to_host(o), to_host(p.legendre_anal(f)))
     assert sht.lib.sht_batch_configure(b._h, 7, 1) == sht.SHT_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mfma"])
+def test_persistent_synthesis_spin_deriv_and_real_harmonics(precision):
+    """The persistent batch synthesis (concurrent 2) for spin-2 plans (FP64 and
+    the FP32 form), derivative maps of spin-1 plans and plans with real
+    spherical harmonics storage: bit for bit the plans' own results, eager and
+    graph-replayed, in both queue orders."""
+    import torch
+    sht = _sht()
+    s = torch.cuda.Stream()
+    cases = []
+    _, plans, alms = _mixed([23, 47], 3, 2, precision)
+    cases.append((plans, [to_dev(a) for a in alms], sht.ALM2MAP))
+    if precision == "fp64":
+        _, plans1, alms0 = _mixed([20, 33], 2, 1)
+        a0 = [to_dev(si.random_alm(p.lmax, p.lmax, 2, 0, tag=7 + k)) for k, p in enumerate(plans1)]
+        cases.append((plans1, a0, sht.ALM2MAP_DERIV1))
+        rplans, ralms = [], []
+        for k, lmax in enumerate([15, 40]):
+            g = si.gauss_geometry(lmax + 1, 2 * lmax + 1)
+            p = sht.Plan(sht.Geometry.from_inputs(g), lmax, spin=0, ntrans=4, real_harmonics=True)
+            rplans.append(p)
+            ralms.append(to_dev(np.random.default_rng(50 + k).standard_normal(p.alm_shape)))
+        cases.append((rplans, ralms, sht.ALM2MAP))
+    for plans, ins, direction in cases:
+        run = "alm2map_deriv1" if direction == sht.ALM2MAP_DERIV1 else "alm2map"
+        refs = [to_host(getattr(p, run)(x)) for p, x in zip(plans, ins)]
+        b = sht.Batch(plans)
+        for order in (sht.QUEUE_COST, sht.QUEUE_MPAIRS):
+            b.configure(order, 2)
+            for stream in (None, s, s):
+                with torch.cuda.stream(s if stream is not None else torch.cuda.current_stream()):
+                    outs = b.execute(direction, ins, stream=stream)
+                torch.cuda.synchronize()
+                for o, r in zip(outs, refs):
+                    assert np.array_equal(to_host(o), r)
+
+
+def test_persistent_synthesis_falls_back_and_follows_retuning():
+    """Plans with different synthesis column blocks cannot share the persistent
+    kernel: the batch runs the plans' own launches (same results); retuning a
+    member to the common shape rebuilds the queue and the captured graph."""
+    import torch
+    sht = _sht()
+    _, plans, alms = _mixed([23, 47], 6, 2)
+    d_alm = [to_dev(a) for a in alms]
+    plans[0].set_tuning(synth_ncb=1)
+    plans[1].set_tuning(synth_ncb=2)
+    b = sht.Batch(plans)
+    b.configure(sht.QUEUE_COST, 2)
+    s = torch.cuda.Stream()
+    for retune in (False, True):
+        if retune:
+            plans[0].set_tuning(synth_ncb=2)
+        refs = [to_host(p.alm2map(a)) for p, a in zip(plans, d_alm)]
+        for stream in (None, s, s):
+            with torch.cuda.stream(s if stream is not None else torch.cuda.current_stream()):
+                outs = b.alm2map(d_alm, stream=stream)
+            torch.cuda.synchronize()
+            for o, r in zip(outs, refs):
+                assert np.array_equal(to_host(o), r)
