@@ -518,27 +518,43 @@ def run_mixed(args):
     res = {}
     with torch.cuda.stream(s):
         res["plans_one_by_one"] = timed(plans_step, args.steps)
-        sched = {"serial": 0, "concurrent": 1, "persistent_synthesis": 2}
-        for conc in ("concurrent", "serial", "persistent_synthesis"):
+        # the persistent synthesis (schedule 2) runs only when every plan is on
+        # the matrix-core kernels with one synthesis shape
+        tun = [p.tuning() for p in plans]
+        eligible = all(t["valu"] == 0 for t in tun) and len({t["synth_ncb"] for t in tun}) == 1
+        sched = {"serial": 0, "concurrent": 1}
+        if eligible:
+            sched["persistent_synthesis"] = 2
+        for conc in sched:
             for order in (sht.QUEUE_COST, sht.QUEUE_MPAIRS):
                 b.configure(order, sched[conc])
                 name = f"batch_{'cost' if order == sht.QUEUE_COST else 'mpairs'}_{conc}"
                 res[name] = timed(batch_step, args.steps)
         best = min((k for k in res if k.startswith("batch")), key=lambda k: res[k])
-        b.configure(sht.QUEUE_MPAIRS if "mpairs" in best else sht.QUEUE_COST,
-                    next(v for k, v in sched.items() if best.endswith(k)))
-        # staged Legendre synthesis as one persistent launch over all plans
-        b.configure(sht.QUEUE_COST, 2)
-        leg_persistent = timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps)
-        b.configure(sht.QUEUE_MPAIRS if "mpairs" in best else sht.QUEUE_COST,
-                    next(v for k, v in sched.items() if best.endswith(k)))
+
+        def use_best():
+            b.configure(sht.QUEUE_MPAIRS if "mpairs" in best else sht.QUEUE_COST,
+                        next(v for k, v in sched.items() if best.endswith(k)))
+
+        # the persistent synthesis against the per-plan chains with every plan on
+        # one matrix-core synthesis shape (the autotuned choice restored after)
+        common = {}
+        for p in plans:
+            p.set_tuning(valu=0, synth_ncb=1)
+        for conc, v in (("concurrent", 1), ("persistent_synthesis", 2)):
+            b.configure(sht.QUEUE_COST, v)
+            common[f"batch_cost_{conc}"] = timed(batch_step, args.steps)
+            common[f"legendre_synth_{conc}"] = timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps)
+        for p, t in zip(plans, tun):
+            p.set_tuning(**t)
+        use_best()
         ms = timed(batch_step, args.steps)
         # staged Legendre steps of the batch (events on the launch stream)
-        leg = {"legendre_synth": timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps),
-               "legendre_synth_persistent": leg_persistent}
+        leg = {"legendre_synth": timed(lambda: b.legendre(sht.ALM2MAP, alms, ph, stream=s), args.steps)}
         b.legendre(sht.ALM2MAP, alms, ph, stream=s)
         leg["legendre_anal"] = timed(lambda: b.legendre(sht.MAP2ALM, ph, back, stream=s), args.steps)
-    log(f"mixed: {res}; chosen {best}: {ms:.2f} ms/pair-step; staged Legendre {leg}")
+    log(f"mixed: {res}; chosen {best}: {ms:.2f} ms/pair-step; staged Legendre {leg}; one matrix-core "
+        f"shape, per-plan chains vs persistent synthesis: {common}")
     f64 = sum(p.flops(sht.MAP2ALM)[0] for p in plans)
     out = base_record(args, 64.0 / (ms * 1e-3), ms, "f64",
                       {"workload": "mixed: 64 scalar transforms, 16 each at lmax 255/511/1023/2047 on "
@@ -546,6 +562,7 @@ def run_mixed(args):
                        "lmaxes": lmaxes, "ntrans_each": 16, "schedule": best})
     out["metric"] = "alm2map+map2alm pairs/sec (mixed batch)"
     out["schedules_ms"] = res
+    out["persistent_synthesis_vs_chains_ms"] = {"tuning": "every plan matrix-core, synth_ncb 1", **common}
     out["batch_speedup_vs_plans"] = res["plans_one_by_one"] / ms
     out["kernels_ms"] = {"batch_legendre": leg}
     achieved = f64 / (leg["legendre_anal"] * 1e-3)
