@@ -991,12 +991,14 @@ __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__re
 
 // ---------------------------------------------------------------- vector path
 //
-// For a few simultaneous spin-0 transforms most matrix-core columns would be
-// empty (2 of 16 for one transform), so the products run on the vector units
-// instead, with no empty columns: every FMA is one of the algorithm's (the
-// loop nests of Sect. 3.2, several ring slots per lane).  A lane runs the
-// recursion chains of K slots (slots lane + 64 k of its tile group), so that
-// each wave-uniform step coefficient serves K chains.  The coefficients of a
+// For one or two spin-0 transforms, or one spin transform, most matrix-core
+// columns would be empty (2 of 16 for one scalar transform, 4 of 16 for one
+// spin transform), so the products run on the vector units instead, with no
+// empty columns: every FMA is one of the algorithm's (the loop nests of Sect.
+// 3.2, several ring slots per lane).  A lane runs the recursion chains of K
+// slots (slots lane + 64 k of its group of 64-slot units; spin: the +s and -s
+// chains of each), so that each wave-uniform step coefficient serves all of
+// them.  The coefficients of a
 // chunk of degrees are loaded with vector loads one chunk ahead, staged in
 // LDS and read back as broadcasts.
 //   synthesis: per degree, per slot the recursion's two FMAs and per transform
@@ -1009,9 +1011,9 @@ __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__re
 //     (permlane32/16 swaps, a DPP mirror) and whose last steps add DPP copies;
 //     the wavefronts' sums are added in LDS in a fixed order (deterministic).
 
-// One step of a chain with the staged coefficients q = (alpha, beta,
-// alpha + beta - 2, alpha - beta - 2) of the degree; MINUS: the -s chain of a
-// spin transform (beta and the difference-form constant of the other sign).
+// One step of a chain with the staged coefficients q = (alpha, beta, delta+,
+// delta-) of the degree, delta+- = alpha +- beta - 2 (the difference form's
+// constant); MINUS: the -s chain of a spin transform (-beta and delta-).
 template <bool DIFF, bool MINUS = false>
 __device__ __forceinline__ void chain_step(Chain &c, const double4 q)
 {
