@@ -112,6 +112,15 @@ void synth_queue(const Batch &b, std::vector<BatchSynItem> &q)
 // while the stream s is being captured.
 int refresh_synth_queue(Batch &b, hipStream_t s, bool force)
 {
+    if (b.concurrent != 2) {   // only schedule 2 uses the queue: built when it is chosen
+        if (b.d_syn) (void)hipDeviceSynchronize();
+        dev_free(b.d_syn);
+        b.d_syn = nullptr;
+        b.nsyn = 0;
+        b.syn_ok = false;
+        b.syn_gen.clear();
+        return SHT_OK;
+    }
     std::vector<uint64_t> gen;
     for (const Plan *p : b.plans) gen.push_back(p->generation);
     if (!force && gen == b.syn_gen) return SHT_OK;
@@ -476,13 +485,14 @@ int sht_batch_configure(sht_batch *h, int queue_order, int concurrent)
     if (concurrent < 0 || concurrent > 2) { set_error("concurrent must be 0, 1 or 2"); return SHT_EINVAL; }
     (void)hipDeviceSynchronize();
     fault_arm();
-    const int old_order = b->queue_order;
+    const int old_order = b->queue_order, old_conc = b->concurrent;
     b->queue_order = queue_order;
     b->concurrent = concurrent;
     int rc = upload_queue(*b);
     if (!rc) rc = refresh_synth_queue(*b, nullptr, true);
-    if (rc) {
+    if (rc) {   // the previous schedule stays
         b->queue_order = old_order;
+        b->concurrent = old_conc;
         (void)upload_queue(*b);
         (void)refresh_synth_queue(*b, nullptr, true);
         return rc;

@@ -81,6 +81,35 @@ def test_injected_allocation_failures_leave_no_buffers():
     assert sht.memory_stats() == mid
 
 
+def test_schedule_change_failing_allocation_keeps_the_batch():
+    """A failed allocation while the persistent synthesis queue is built
+    (sht_batch_configure with concurrent 2) gives SHT_ENOMEM, keeps the previous
+    schedule and the batch's results, and leaks nothing; switching back to the
+    per-plan schedule releases the queue."""
+    sht = _sht()
+    lmax = 31
+    g = sht.Geometry.from_inputs(si.gauss_geometry(lmax + 1, 2 * lmax + 1))
+    plans = [sht.Plan(g, lmax, spin=2, ntrans=3) for _ in range(2)]
+    a = [to_dev(si.random_alm(lmax, lmax, 3, 2, tag=9 + k)) for k in range(2)]
+    b = sht.Batch(plans)
+    ref = [to_host(m) for m in b.alm2map(a)]
+    base = sht.memory_stats()
+    os.environ["SHT_FAULT_INJECT"] = "alloc:2"   # 1: analysis queue, 2: synthesis queue
+    try:
+        with pytest.raises(sht.ShtError) as e:
+            b.configure(sht.QUEUE_COST, 2)
+        assert e.value.status == sht.SHT_ENOMEM
+    finally:
+        del os.environ["SHT_FAULT_INJECT"]
+    assert sht.memory_stats() == base
+    assert all(np.array_equal(to_host(m), r) for m, r in zip(b.alm2map(a), ref))
+    b.configure(sht.QUEUE_COST, 2)
+    assert sht.memory_stats()[0] == base[0] + 1   # the synthesis queue
+    assert all(np.array_equal(to_host(m), r) for m, r in zip(b.alm2map(a), ref))
+    b.configure(sht.QUEUE_COST, 1)
+    assert sht.memory_stats() == base
+
+
 def test_destroyed_plan_rejected_by_execute_and_batch():
     import torch
     sht = _sht()
