@@ -71,39 +71,59 @@ void anal_queue(const Batch &b, std::vector<BatchAnaItem> &q)
 
 // Queue of synthesis items of all plans (persistent synthesis): one item per
 // (plan, m, slot tile active at m, transform group of the plan's column
-// blocks); SHT_QUEUE_COST: by decreasing degree range; SHT_QUEUE_MPAIRS: the
-// same tile and group at m and mmax - m in one item, by decreasing pair cost.
-void synth_queue(const Batch &b, std::vector<BatchSynItem> &q)
+// blocks); SHT_QUEUE_MPAIRS: the same tile and group at m and mmax - m in one
+// item.  Items come in blocks of the plan's synth_mblock consecutive m (of the
+// first m of a pair), and every block goes to one die's segment (the least
+// loaded, blocks by decreasing cost), so that the lines of F that a block
+// writes stay in one die's L2; within a segment, items by decreasing cost.
+void synth_queue(Batch &b, std::vector<BatchSynItem> &q)
 {
     const int cpj = b.spin ? 4 : 2;
-    std::vector<std::pair<double, BatchSynItem>> v;
+    using Item = std::pair<double, BatchSynItem>;
+    struct Block {
+        double cost = 0.0;
+        std::vector<Item> items;
+    };
+    std::vector<Block> blocks;
     for (int pi = 0; pi < (int)b.plans.size(); ++pi) {
         const Plan &p = *b.plans[pi];
         const int jpg = p.tune.synth_ncb * 16 / cpj;
+        const int MB = std::max(1, p.tune.synth_mblock);
         auto lrange = [&](int m) { return (double)(p.lmax + 1 - std::max(m, p.spin)); };
-        if (b.queue_order == SHT_QUEUE_MPAIRS) {
-            for (int m = 0; m <= p.mmax - m; ++m) {
-                const int m2 = p.mmax - m;
+        const bool pairs = b.queue_order == SHT_QUEUE_MPAIRS;
+        const int mend = pairs ? p.mmax / 2 : p.mmax;   // last first-m of an item
+        for (int m0 = 0; m0 <= mend; m0 += MB) {
+            Block blk;
+            for (int m = m0; m <= std::min(mend, m0 + MB - 1); ++m) {
+                const int m2 = pairs ? p.mmax - m : -1;
                 for (int t = 0; t < p.ntiles; ++t) {
-                    const bool a1 = p.tile_mlim[t] >= m, a2 = m2 != m && p.tile_mlim[t] >= m2;
+                    const bool a1 = p.tile_mlim[t] >= m, a2 = pairs && m2 != m && p.tile_mlim[t] >= m2;
                     if (!a1 && !a2) continue;
                     const double c = (a1 ? lrange(m) : 0.0) + (a2 ? lrange(m2) : 0.0);
-                    for (int t0 = 0; t0 < p.ntrans; t0 += jpg)
-                        v.push_back({c, BatchSynItem{pi, a1 ? m : m2, (a1 && a2) ? m2 : -1, t, t0, {0, 0, 0}}});
+                    for (int t0 = 0; t0 < p.ntrans; t0 += jpg) {
+                        blk.items.push_back({c, BatchSynItem{pi, a1 ? m : m2, (a1 && a2) ? m2 : -1, t, t0, {0, 0, 0}}});
+                        blk.cost += c;
+                    }
                 }
             }
-        } else {
-            for (int m = 0; m <= p.mmax; ++m)
-                for (int t = 0; t < p.ntiles; ++t) {
-                    if (p.tile_mlim[t] < m) continue;
-                    for (int t0 = 0; t0 < p.ntrans; t0 += jpg)
-                        v.push_back({lrange(m), BatchSynItem{pi, m, -1, t, t0, {0, 0, 0}}});
-                }
+            if (!blk.items.empty()) blocks.push_back(std::move(blk));
         }
     }
-    std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
+    std::stable_sort(blocks.begin(), blocks.end(), [](const Block &a, const Block &c) { return a.cost > c.cost; });
+    std::vector<std::vector<Item>> die(NUM_XCD);
+    std::vector<double> load(NUM_XCD, 0.0);
+    for (Block &blk : blocks) {
+        const int d = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[d] += blk.cost;
+        die[d].insert(die[d].end(), blk.items.begin(), blk.items.end());
+    }
     q.clear();
-    for (auto &e : v) q.push_back(e.second);
+    for (int d = 0; d < NUM_XCD; ++d) {
+        std::stable_sort(die[d].begin(), die[d].end(), [](const Item &a, const Item &c) { return a.first > c.first; });
+        b.syn_ofs[d] = (int)q.size();
+        for (auto &e : die[d]) q.push_back(e.second);
+    }
+    b.syn_ofs[NUM_XCD] = (int)q.size();
 }
 
 // (Re)builds the synthesis queue when the plans' work lists changed since it
@@ -117,6 +137,7 @@ int refresh_synth_queue(Batch &b, hipStream_t s, bool force)
         dev_free(b.d_syn);
         b.d_syn = nullptr;
         b.nsyn = 0;
+        for (int &o : b.syn_ofs) o = 0;
         b.syn_ok = false;
         b.syn_gen.clear();
         return SHT_OK;
@@ -138,18 +159,28 @@ int refresh_synth_queue(Batch &b, hipStream_t s, bool force)
     dev_free(b.d_syn);
     b.d_syn = nullptr;
     b.nsyn = 0;
-    b.syn_gen = gen;
-    if (!b.syn_ok) return SHT_OK;
+    for (int &o : b.syn_ofs) o = 0;
+    b.syn_gen.clear();
+    if (!b.syn_ok) {
+        b.syn_gen = gen;
+        return SHT_OK;
+    }
     b.syn_ncb = p0.tune.synth_ncb;
     b.syn_flush = p0.flush_chunks;
     b.syn_groups = synth_batch_groups(b.spin, b.syn_ncb, b.precision == SHT_FP32_MFMA, b.device);
     std::vector<BatchSynItem> q;
     synth_queue(b, q);
-    int rc;
-    if ((rc = dev_alloc((void **)&b.d_syn, std::max<size_t>(1, q.size()) * sizeof(BatchSynItem), "batch tables")))
+    int rc = dev_alloc((void **)&b.d_syn, std::max<size_t>(1, q.size()) * sizeof(BatchSynItem), "batch tables");
+    if (!rc && !q.empty()) rc = dev_upload(b.d_syn, q.data(), q.size() * sizeof(BatchSynItem), "batch tables");
+    if (rc) {   // no queue: the plans' own launches run until a later call builds it
+        dev_free(b.d_syn);
+        b.d_syn = nullptr;
+        for (int &o : b.syn_ofs) o = 0;
+        b.syn_ok = false;
         return rc;
+    }
     b.nsyn = (int)q.size();
-    if (!q.empty()) return dev_upload(b.d_syn, q.data(), q.size() * sizeof(BatchSynItem), "batch tables");
+    b.syn_gen = gen;
     return SHT_OK;
 }
 
@@ -446,7 +477,7 @@ int sht_batch_create(int nplans, sht_plan *const *plans, sht_batch **out)
     if ((rc = dev_alloc((void **)&b->d_views, views.size() * sizeof(LegView), "batch tables")) ||
         (rc = dev_upload(b->d_views, views.data(), views.size() * sizeof(LegView), "batch tables")) ||
         (rc = upload_queue(*b)) || (rc = refresh_synth_queue(*b, nullptr, true)) ||
-        (rc = dev_alloc((void **)&b->d_counter, 128, "batch counter"))) {
+        (rc = dev_alloc((void **)&b->d_counter, 64 * (NUM_XCD + 2), "batch counters"))) {
         batch_free(b);
         delete b;
         return rc;

@@ -962,22 +962,32 @@ __global__ __launch_bounds__(64 * ana_nw(F32, SPIN != 0), 2) void k_legendre_ana
     }
 }
 
-// Persistent synthesis for a batch of plans: every wavefront takes items from
-// one queue (atomic counter) until it is empty; all lanes read the same index,
-// so the whole wavefront leaves together.
+// Persistent synthesis for a batch of plans: the queue has one segment per
+// accelerator die (blocks of consecutive m of a plan on one die, as in the
+// plans' own item lists), each with its own counter 64 bytes apart.  A
+// wavefront takes items from its die's segment (work groups go to the dies
+// round robin), then from the others' until every segment is empty; all lanes
+// read the same index, so the whole wavefront moves on and leaves together.
 template <int SPIN, int NCB, bool F32>
 __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__restrict__ views,
-                                                             const BatchSynItem *__restrict__ items, int nitems,
+                                                             const BatchSynItem *__restrict__ items, SynQueues q,
                                                              BatchPtrs ptrs, int flush_chunks, int deriv,
-                                                             unsigned *counter)
+                                                             unsigned *counters)
 {
     __shared__ SynShared<SPIN, F32> sh;
+    const int die = (int)(blockIdx.x % NUM_XCD);
+    int k = 0;
     for (;;) {
+        const int d = (die + k) % NUM_XCD;
+        const unsigned n = (unsigned)(q.ofs[d + 1] - q.ofs[d]);
         unsigned got = 0;
-        if (threadIdx.x == 0) got = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) got = atomicAdd(counters + 16 * d, 1u);
         const unsigned idx = __builtin_amdgcn_readfirstlane(got);   // lane 0's value
-        if (idx >= (unsigned)nitems) break;
-        const BatchSynItem bi = items[idx];
+        if (idx >= n) {
+            if (++k == NUM_XCD) break;   // every segment empty
+            continue;
+        }
+        const BatchSynItem bi = items[q.ofs[d] + idx];
         synth_item<SPIN, NCB, F32>(views[bi.plan], WaveItem{bi.m, bi.tile, bi.t0, 0}, ptrs.in[bi.plan],
                                    ptrs.out[bi.plan], flush_chunks, deriv, sh);
         __syncthreads();   // this item's LDS reads are done before the next item's writes
@@ -1853,6 +1863,12 @@ __global__ void k_reset_counter(unsigned *counter)
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
+// n counters `stride` apart (one work group of at least n threads)
+__global__ void k_reset_counters(unsigned *counter, int n, int stride)
+{
+    if ((int)threadIdx.x < n) counter[threadIdx.x * stride] = 0u;
+}
+
 // ---------------------------------------------------------------- launchers
 
 // column blocks (16 columns each) per analysis work group: bounded so that
@@ -2110,10 +2126,12 @@ int synth_batch_groups(int spin, int ncb, bool f32, int dev)
 template <int SPIN, int NCB, bool F32>
 static void launch_synth_batch_t(const Batch &b, const BatchPtrs &ptrs, int deriv, hipStream_t s)
 {
-    unsigned *counter = b.d_counter + 16;
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    unsigned *counters = b.d_counter + 16;
+    SynQueues q;
+    for (int d = 0; d <= NUM_XCD; ++d) q.ofs[d] = b.syn_ofs[d];
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, NUM_XCD, 16);
     hipLaunchKernelGGL((k_legendre_synth_batch<SPIN, NCB, F32>), dim3((unsigned)b.syn_groups), dim3(64), 0, s,
-                       b.d_views, b.d_syn, b.nsyn, ptrs, b.syn_flush, deriv, counter);
+                       b.d_views, b.d_syn, q, ptrs, b.syn_flush, deriv, counters);
 }
 
 int launch_legendre_synth_batch(const Batch &b, const BatchPtrs &ptrs, bool deriv, hipStream_t s)

@@ -50,6 +50,10 @@ struct BatchSynItem {
     int t0;
     int pad[3];
 };
+// Segment offsets of the synthesis queue, one segment per accelerator die.
+struct SynQueues {
+    int ofs[NUM_XCD + 1];
+};
 
 // Device-side view of one plan for the Legendre kernels.
 struct LegView {
@@ -163,12 +167,13 @@ struct Batch {
     int nana = 0;
     LegView *d_views = nullptr;
     BatchAnaItem *d_ana = nullptr;
-    unsigned *d_counter = nullptr;       // [0]: analysis queue, [16]: synthesis queue
+    unsigned *d_counter = nullptr;       // [0]: analysis queue, [16 (1 + d)]: synthesis queue of die d
     // persistent synthesis (concurrent == 2): one queue over all plans, built
     // for the plans' tunings at the generations in syn_gen; syn_ok: every plan
     // on the matrix-core path with the same column blocks and carry interval
     bool syn_ok = false;
     int nsyn = 0, syn_groups = 1, syn_ncb = 1, syn_flush = 4;
+    int syn_ofs[NUM_XCD + 1] = {};       // items of die d: d_syn[syn_ofs[d] .. syn_ofs[d + 1])
     BatchSynItem *d_syn = nullptr;
     std::vector<uint64_t> syn_gen;
     // captured graphs, one per direction, keyed by the user pointers and the
