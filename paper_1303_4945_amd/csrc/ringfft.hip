@@ -58,7 +58,7 @@ struct FftLen {         // complex transform of length L
     int64_t bhat_p;     // kernel spectrum for sign +  (M entries; split: even half then odd half)
     int64_t bhat_m;     // kernel spectrum for sign -
     int64_t wm;         // split: e^{-2 pi i n / M}, n < M/2
-    int64_t gpow;       // Rader: itab offset of g^p mod L, p < L-1
+    int64_t rpos;       // Rader: itab offset of the LDS position of x_n, n < L: p with g^p = n, L-1 for n = 0
     int64_t qpos;       // Rader: itab offset of q(k) with g^{-q} = k mod L, 0 < k < L
     int lds_complex;    // LDS buffer size in complex elements
 };
@@ -678,9 +678,9 @@ __device__ __forceinline__ double2 fold_bin_single(const FftView &fv, const doub
 // Rader's algorithm for a prime length L with smooth L-1: with a generator g
 // of the multiplicative group mod L, a_p = x_{g^p} and b_q = w^{g^{-q}}
 // (w = e^{-+2 pi i / L}), X_{g^{-q}} = x_0 + (a (*) b)_q, a cyclic convolution of
-// length L-1 done with two in-LDS transforms.  buf holds x_n in natural order
-// on entry; on return buf[q] holds (a (*) b)_q, and x0 = x_0, X0 = X_0 = sum x_n.
-// Requires FFT_NREG * blockDim.x >= L - 1.
+// length L-1 done with two in-LDS transforms.  buf holds a_p at p < L-1 and x_0
+// at L-1 on entry (the input is stored there directly, no reordering pass); on
+// return buf[q] holds (a (*) b)_q, and x0 = x_0, X0 = X_0 = sum x_n.
 struct RaderEnds {
     double2 x0, X0;
 };
@@ -690,26 +690,8 @@ __device__ __forceinline__ RaderEnds rader(double2 *buf, const FftView &fv, cons
 {
     const FftInner &in = fv.inner[d.inner];
     const int Lm = d.L - 1;
-    const int *gp = fv.itab + d.gpow;
     const double2 *bh = fv.ctab + (fwd ? d.bhat_m : d.bhat_p);
-    // staged as separate real arrays: element-wise copies of double2 between
-    // LDS and a private array keep the array out of registers
-    double are[FFT_NREG], aim[FFT_NREG];
-    const double2 x0 = buf[padi<POW2>(0)];
-#pragma unroll
-    for (int j = 0; j < FFT_NREG; ++j) {
-        const int p = threadIdx.x + j * blockDim.x;
-        const double2 t = buf[padi<POW2>(p < Lm ? gp[p] : 0)];
-        are[j] = t.x;
-        aim[j] = t.y;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < FFT_NREG; ++j) {
-        const int p = threadIdx.x + j * blockDim.x;
-        if (p < Lm) buf[padi<POW2>(p)] = make_double2(are[j], aim[j]);
-    }
-    __syncthreads();
+    const double2 x0 = buf[padi<POW2>(Lm)];
     fft_dif<POW2, POW2>(buf, in, true, fv.ctab);
     const double2 A0 = buf[padi<POW2>(0)];        // DC of the reordered input: sum_{n>0} x_n
     __syncthreads();
@@ -750,7 +732,8 @@ __device__ __forceinline__ SpecRead<MODE, lds_pad<MODE, POW2>()> ring_transform(
     if constexpr (MODE == KMODE_SPLIT) {
         bluestein_split<FFT_NREG, POW2>(buf, fv, d, fwd, load);
     } else if constexpr (MODE == KMODE_RADER) {
-        batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[padi<POW2>(n)] = v; });
+        const int *rp = fv.itab + d.rpos;   // x_n goes straight to its place in Rader's order
+        batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[padi<POW2>(rp[n])] = v; });
         __syncthreads();
         const RaderEnds e = rader<POW2>(buf, fv, d, fwd);
         r.x0 = e.x0;
@@ -1202,11 +1185,13 @@ static int add_len(FftHost &H, int L, int cmax, int &err)
         d.kind = FFT_RADER;
         d.M = L - 1;
         d.inner = add_inner(H, L - 1);
-        d.lds_complex = L;       // the natural-order input before the reordering
+        d.lds_complex = L;       // the reordered input and x_0
         const int g = primitive_root(L);
         const int ginv = (int)powmod(g, L - 2, L);
-        d.gpow = (int64_t)H.itab.size();
-        for (int64_t p = 0, v = 1; p < L - 1; ++p, v = v * g % L) H.itab.push_back((int)v);
+        d.rpos = (int64_t)H.itab.size();
+        H.itab.resize(H.itab.size() + L, 0);
+        H.itab[d.rpos] = L - 1;   // x_0 after the L - 1 reordered values
+        for (int64_t p = 0, v = 1; p < L - 1; ++p, v = v * g % L) H.itab[d.rpos + v] = (int)p;   // g^p = v
         d.qpos = (int64_t)H.itab.size();
         H.itab.resize(H.itab.size() + L, 0);
         d.chirp = (int64_t)H.ctab.size();
