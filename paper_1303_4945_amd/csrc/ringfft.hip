@@ -82,6 +82,7 @@ struct FftView {
     const double *weight;
     const double2 *rot;      // per ring: 64 fine + ncoarse coarse rotations e^{i m phi0}
     int nrot;                // entries per ring
+    int rot_trivial;         // 1: phi0 = 0 on every ring (no rotation)
     const int *mvalid;       // per ring: largest meaningful m
     int mmax, nrings, ncomp;
     int64_t npix;
@@ -647,15 +648,25 @@ __device__ __forceinline__ double2 ring_rot(const FftView &fv, int y, int m)
     return cmul(r[m & 63], r[64 + (m >> 6)]);
 }
 
+// a e^{i m phi0} (conj: a e^{-i m phi0}); no table loads where every ring starts at phi = 0
+__device__ __forceinline__ double2 rotate(const FftView &fv, double2 a, int y, int m)
+{
+    return fv.rot_trivial ? a : cmul(a, ring_rot(fv, y, m));
+}
+__device__ __forceinline__ double2 rotate_conj(const FftView &fv, double2 a, int y, int m)
+{
+    return fv.rot_trivial ? a : cmul(a, cconj(ring_rot(fv, y, m)));
+}
+
 // Folded Hermitian spectrum bin k of ring y for component row `row`:
 // b_k = sum over m = k mod N, |m| <= mv, of F_m e^{i m phi0} (conjugated for m < 0).
 __device__ __forceinline__ double2 fold_bin(const FftView &fv, const double2 *Frow, int y, int N, int mv, int k)
 {
     double2 s = make_double2(0.0, 0.0);
-    for (int m = k; m <= mv; m += N) s = cadd(s, cmul(Frow[m], ring_rot(fv, y, m)));
+    for (int m = k; m <= mv; m += N) s = cadd(s, rotate(fv, Frow[m], y, m));
     for (int m = N - k; m <= mv; m += N) {
         if (m == 0) continue;
-        s = cadd(s, cconj(cmul(Frow[m], ring_rot(fv, y, m))));
+        s = cadd(s, cconj(rotate(fv, Frow[m], y, m)));
     }
     return s;
 }
@@ -670,7 +681,7 @@ __device__ __forceinline__ double2 fold_bin_single(const FftView &fv, const doub
     const int m = refl ? N - k : k;
     const bool ok = m <= mv;
     const int mc = ok ? m : 0;
-    const double2 t = cmul(Frow[mc], ring_rot(fv, y, mc));
+    const double2 t = rotate(fv, Frow[mc], y, mc);
     const double2 z = refl ? cconj(t) : t;
     return ok ? z : make_double2(0.0, 0.0);
 }
@@ -870,8 +881,7 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
                 const double2 dd = csub(Zk, Zc);
                 const double2 S = side ? make_double2(0.5 * dd.y, -0.5 * dd.x)
                                        : make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
-                const double2 r = cconj(ring_rot(fv, y, m));
-                const double2 g = cmul(S, r);
+                const double2 g = rotate_conj(fv, S, y, m);
                 return make_double2(w * g.x, w * g.y);
             }, [&](int m, double2 g) { G[m] = g; });
         }
@@ -902,8 +912,7 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             const double2 tw = k < h ? t : make_double2(-1.0, 0.0);   // k == h: e^{-i pi}
             double2 X = cadd(E, cmul(tw, O));
             if (cj) X = cconj(X);
-            const double2 r = cconj(ring_rot(fv, y, m));
-            const double2 g = cmul(X, r);
+            const double2 g = rotate_conj(fv, X, y, m);
             return make_double2(w * g.x, w * g.y);
         }, [&](int m, double2 g) { G[m] = g; });
     }
@@ -1283,6 +1292,7 @@ struct FftDev {
     double2 *rot = nullptr;
     int *mvalid = nullptr;
     int nrot = 0;
+    int rot_trivial = 0;      // every ring has phi0 = 0
     std::vector<FftGroup> groups;
     std::vector<int *> group_rows;
     // plans with several ring-length groups run the groups' launches on
@@ -1312,6 +1322,7 @@ static FftView view_of(const Plan &p, const FftDev &D)
     v.weight = D.weight;
     v.rot = D.rot;
     v.nrot = D.nrot;
+    v.rot_trivial = D.rot_trivial;
     v.mvalid = D.mvalid;
     v.mmax = p.mmax;
     v.nrings = p.geom.nrings;
@@ -1437,6 +1448,7 @@ int fft_plan_build(Plan &p)
         return rc;
     }
     D->nrot = nrot;
+    D->rot_trivial = std::all_of(g.phi0.begin(), g.phi0.end(), [](double x) { return x == 0.0; }) ? 1 : 0;
     for (auto &gr : D->groups) {
         int *dr = nullptr;
         if ((rc = up((void **)&dr, gr.rows.data(), gr.rows.size() * sizeof(int), "fft rows"))) {
