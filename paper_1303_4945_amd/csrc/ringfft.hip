@@ -868,23 +868,30 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             return make_double2(a, b);
         };
         const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
-        for (int side = 0; side < (row.yb >= 0 ? 2 : 1); ++side) {
-            const int y = side ? row.yb : row.ya;
-            const int mv = min(fv.mvalid[y], fv.mmax);
-            const double w = use_weights ? fv.weight[y] : 1.0;
-            double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
-            batched_loop<false, LOOP_U>(mv + 1, [&](int m) {
-                const int k = m % N;
-                const int kc = (N - k) % N;
-                const double2 Zk = rd(k), Zc = cconj(rd(kc));
-                // side 0: (Zk + Zc) / 2; side 1: (Zk - Zc) / (2i)
-                const double2 dd = csub(Zk, Zc);
-                const double2 S = side ? make_double2(0.5 * dd.y, -0.5 * dd.x)
-                                       : make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
-                const double2 g = rotate_conj(fv, S, y, m);
-                return make_double2(w * g.x, w * g.y);
-            }, [&](int m, double2 g) { G[m] = g; });
-        }
+        // ring a: (Zk + conj Z_(N-k)) / 2, ring b: (Zk - conj Z_(N-k)) / (2i), both
+        // from one read of the two bins
+        const bool hasb = row.yb >= 0;
+        const int yb = hasb ? row.yb : row.ya;
+        const int mva = min(fv.mvalid[row.ya], fv.mmax), mvb = hasb ? min(fv.mvalid[yb], fv.mmax) : -1;
+        const double wa = use_weights ? fv.weight[row.ya] : 1.0, wb = use_weights ? fv.weight[yb] : 1.0;
+        double2 *Ga = reinterpret_cast<double2 *>(phase) + (rowF + row.ya) * (fv.mmax + 1);
+        double2 *Gb = reinterpret_cast<double2 *>(phase) + (rowF + yb) * (fv.mmax + 1);
+        struct GPair {
+            double2 a, b;
+        };
+        batched_loop<false, LOOP_U>(max(mva, mvb) + 1, [&](int m) {
+            const int k = m % N;
+            const int kc = (N - k) % N;
+            const double2 Zk = rd(k), Zc = cconj(rd(kc));
+            const double2 dd = csub(Zk, Zc);
+            const double2 Sa = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
+            const double2 Sb = make_double2(0.5 * dd.y, -0.5 * dd.x);
+            const double2 ga = rotate_conj(fv, Sa, row.ya, m), gb = rotate_conj(fv, Sb, yb, m);
+            return GPair{make_double2(wa * ga.x, wa * ga.y), make_double2(wb * gb.x, wb * gb.y)};
+        }, [&](int m, GPair g) {
+            if (m <= mva) Ga[m] = g.a;
+            if (m <= mvb) Gb[m] = g.b;
+        });
     } else {
         const int h = N / 2;
         auto xin = [&](int n) {
