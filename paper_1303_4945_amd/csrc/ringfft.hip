@@ -862,10 +862,15 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
     const double *mp = map + (int64_t)tc * fv.npix;
 
     if (row.mode == ROW_PAIR) {
+        // row pointers hoisted out of the element loop; ring b absent: ring a
+        // is read a second time and replaced by zero (a select, no branch)
+        const double *pa = mp + fv.ofs[row.ya];
+        const bool hb = row.yb >= 0;
+        const double *pb = mp + fv.ofs[hb ? row.yb : row.ya];
+        const int64_t st = fv.stride;
         auto xin = [&](int x) {
-            double a = mp[fv.ofs[row.ya] + (int64_t)x * fv.stride];
-            double b = row.yb >= 0 ? mp[fv.ofs[row.yb] + (int64_t)x * fv.stride] : 0.0;
-            return make_double2(a, b);
+            const double b = pb[(int64_t)x * st];
+            return make_double2(pa[(int64_t)x * st], hb ? b : 0.0);
         };
         const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
         // ring a: (Zk + conj Z_(N-k)) / 2, ring b: (Zk - conj Z_(N-k)) / (2i), both
@@ -894,11 +899,9 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
         });
     } else {
         const int h = N / 2;
-        auto xin = [&](int n) {
-            double a = mp[fv.ofs[row.ya] + (int64_t)(2 * n) * fv.stride];
-            double b = mp[fv.ofs[row.ya] + (int64_t)(2 * n + 1) * fv.stride];
-            return make_double2(a, b);
-        };
+        const double *pa = mp + fv.ofs[row.ya];
+        const int64_t st = fv.stride;
+        auto xin = [&](int n) { return make_double2(pa[(int64_t)(2 * n) * st], pa[(int64_t)(2 * n + 1) * st]); };
         const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
         const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}, k < h
         const int y = row.ya;
