@@ -169,6 +169,22 @@ def test_valu_spin_batch_equals_plans():
             assert np.array_equal(to_host(ab), to_host(p.map2alm(mp)))
 
 
+@pytest.mark.parametrize("spin", [0, 2])
+def test_valu_deterministic(spin):
+    """Repeated runs of the vector kernels give the same bits (fixed-order
+    butterfly and work-group sums, no atomics)."""
+    sht = _sht()
+    g = si.healpix_geometry(32)
+    lmax = 80
+    p = sht.Plan(sht.Geometry.from_inputs(g), lmax, spin=spin, ntrans=1)
+    assert p.tuning()["valu"] == 1
+    a = to_dev(si.random_alm(lmax, lmax, 1, spin, tag=61))
+    m1, m2 = to_host(p.alm2map(a)), to_host(p.alm2map(a))
+    assert np.array_equal(m1, m2)
+    x = to_dev(m1)
+    assert np.array_equal(to_host(p.map2alm(x)), to_host(p.map2alm(x)))
+
+
 def test_valu_unsupported_combinations_rejected():
     sht = _sht()
     g = sht.Geometry.from_inputs(si.gauss_geometry(16, 31))
