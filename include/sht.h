@@ -322,6 +322,13 @@ int sht_plan_set_tuning(sht_plan *p, const sht_tuning *t);
    hold the plan capture their launches again at their next execution. */
 int sht_autotune(sht_plan *p, double budget_seconds);
 
+/* Message of the calling thread's last failed call ("" if none).
+   Diagnostics: the environment variable SHT_LOG (read once per process) writes
+   one line per event to stderr -- 1: handles created and destroyed, tunings and
+   recorded errors; 2: also every call of sht_execute, sht_legendre,
+   sht_ring_fft and the batch entry points; 3: also every kernel launch.  Every
+   entry point that does work opens a roctx range named after itself, which ROCm
+   tracers (rocprofv3 --marker-trace) record beside the kernels. */
 const char *sht_last_error(void);
 const char *sht_strerror(int status);
 
