@@ -1482,19 +1482,17 @@ __device__ __forceinline__ double dpp_half_add(double a, double b, bool upper)
     return keep + dpp_f64(send, CTRL);
 }
 
-// x[0..7] of every lane -> every lane L holds the sum over all 64 lanes of
-// x[L >> 3] (halving steps over lane bits 5, 4 and 3, then plain sums over the
-// lanes that differ in bits 0-2).
-__device__ __forceinline__ double wave_reduce8(double (&x)[8], int lane)
+// x[0..7] of every lane -> every lane L holds a partial sum of x[L >> 3] over
+// 8 of the 64 lanes (halving steps over lane bits 5, 4 and 3); the 8 lanes of
+// an octet (lane bits 0-2) hold the 8 partial sums of the same value, whose
+// total the caller forms later (once per output element rather than per group).
+__device__ __forceinline__ double wave_reduce8_octet(double (&x)[8], int lane)
 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) x[i] = swap32_add(x[i], x[i + 4]);   // index i + 4 b5
 #pragma unroll
     for (int i = 0; i < 2; ++i) x[i] = swap16_add(x[i], x[i + 2]);   // + 2 b4
-    double r = dpp_half_add<0x140>(x[0], x[1], lane & 8);            // row mirror: + b3
-    r += dpp_f64(r, 0x141);                                           // lanes L ^ 7
-    r += dpp_f64(r, 0x4E);                                            // L ^ 2
-    return r + dpp_f64(r, 0xB1);                                      // L ^ 1
+    return dpp_half_add<0x140>(x[0], x[1], lane & 8);                // row mirror: + b3
 }
 
 constexpr int ANV_NW = 4;   // wavefronts per analysis work group (vector path)
@@ -1513,7 +1511,9 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
     constexpr int GD = 4 / J;            // degrees per reduction group: 8 values
     static_assert(GD * J * 2 == 8 && LC % GD == 0 && LC <= 64, "value layout");
     constexpr int OPT = (NV + 63) / 64;  // output values per thread (at least one wavefront)
-    __shared__ double part[2][ANV_NW][NV];
+    constexpr int NWM = J == 1 ? 2 : ANV_NW;   // wavefronts per work group at most (launcher)
+    // per wavefront, value and octet lane: the octet's 8 partial sums of the value
+    __shared__ double part[2][NWM][NV * 8];
     __shared__ double4 stq[2][LC];
     const int m = mlist[blockIdx.x];
     const int t0 = (int)blockIdx.y * J;
@@ -1632,8 +1632,8 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
                 }
             };
             auto gend = [&](int g0) {
-                const double r = wave_reduce8(x, lane);
-                if ((lane & 7) == 0) part[buf][wave][(g0 / GD) * 8 + (lane >> 3)] = r;
+                // lane L: partial sum of value (g0 / GD) 8 + (L >> 3), slot L & 7
+                part[buf][wave][(g0 / GD) * 64 + lane] = wave_reduce8_octet(x, lane);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) x[i] = 0.0;
             };
@@ -1641,7 +1641,7 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
                 if (diff) chains_chunk<LC, GD, K, true, 1>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
                 else chains_chunk<LC, GD, K, false, 1>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
             } else {
-                for (int e = lane; e < NV; e += 64) part[buf][wave][e] = 0.0;
+                for (int e = lane; e < NV * 8; e += 64) part[buf][wave][e] = 0.0;
             }
             if (more) stage(buf ^ 1, lc + LC);
             __syncthreads();
@@ -1650,8 +1650,12 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu(LegView v, c
                 const int e = tid + j * (int)blockDim.x;
                 const int t = (e >> 1) / J, ol = lc + t;
                 if (!o_valid(e) || ol > lmax) continue;
-                double sum = part[buf][0][e];
-                for (int w = 1; w < nw; ++w) sum += part[buf][w][e];
+                double sum = 0.0;   // wavefronts and octet slots in a fixed order
+                for (int w = 0; w < nw; ++w) {
+                    const double *pw = &part[buf][w][e * 8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) sum += pw[q];
+                }
                 double val = sum * stq[buf][t].w * fac;
                 if (m == 0 && (e & 1)) val = 0.0;
                 orow(e)[2 * (int64_t)ol] = first ? val : prev[j] + val;
@@ -1683,7 +1687,8 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu_s(LegView v,
     constexpr int GD = 2;                  // degrees per reduction group: 8 values (one transform)
     static_assert(J == 1 && LC % GD == 0 && LC <= 64, "value layout");
     constexpr int OPT = (NV + 63) / 64;
-    __shared__ double part[2][ANV_NW][NV];
+    constexpr int NWM = 2;   // wavefronts per work group at most (launcher)
+    __shared__ double part[2][NWM][NV * 8];   // octet partial sums per value
     __shared__ double4 stq[2][LC];
     __shared__ double stf[2][LC];
     const int m = mlist[blockIdx.x];
@@ -1828,8 +1833,8 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu_s(LegView v,
                 }
             };
             auto gend = [&](int g0) {
-                const double r = wave_reduce8(x, lane);
-                if ((lane & 7) == 0) part[buf][wave][(g0 / GD) * 8 + (lane >> 3)] = r;
+                // lane L: partial sum of value (g0 / GD) 8 + (L >> 3), slot L & 7
+                part[buf][wave][(g0 / GD) * 64 + lane] = wave_reduce8_octet(x, lane);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) x[i] = 0.0;
             };
@@ -1837,7 +1842,7 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu_s(LegView v,
                 if (diff) chains_chunk<LC, GD, 2 * K, true, 2>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
                 else chains_chunk<LC, GD, 2 * K, false, 2>(cs, slow, l0, lc, lmax, thr, down, load, emit, gend);
             } else {
-                for (int e = lane; e < NV; e += 64) part[buf][wave][e] = 0.0;
+                for (int e = lane; e < NV * 8; e += 64) part[buf][wave][e] = 0.0;
             }
             if (more) stage(buf ^ 1, lc + LC);
             __syncthreads();
@@ -1846,8 +1851,12 @@ __global__ __launch_bounds__(64 * ANV_NW) void k_legendre_anal_valu_s(LegView v,
                 const int e = tid + j * (int)blockDim.x;
                 const int t = (e >> 2) / J, ol = lc + t;
                 if (!o_valid(e) || ol > lmax || ol < m) continue;
-                double sum = part[buf][0][e];
-                for (int w = 1; w < nw; ++w) sum += part[buf][w][e];
+                double sum = 0.0;   // wavefronts and octet slots in a fixed order
+                for (int w = 0; w < nw; ++w) {
+                    const double *pw = &part[buf][w][e * 8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) sum += pw[q];
+                }
                 double val = sum * stf[buf][t] * fac;
                 if (m == 0 && (e & 1)) val = 0.0;
                 orow(e)[2 * (int64_t)ol] = first ? val : prev[j] + val;
