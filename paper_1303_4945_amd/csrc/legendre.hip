@@ -1017,9 +1017,9 @@ __global__ __launch_bounds__(64) void k_legendre_synth_batch(const LegView *__re
 //   analysis: per degree, per slot two FMAs per transform with the stationary
 //     phases G_t +- G_(pi-t) of the slot, summed over the lane's K slots in
 //     registers; every few degrees the 64 lanes' partial sums (8 values) are
-//     reduced by a butterfly whose first steps halve the values a lane holds
-//     (permlane32/16 swaps, a DPP mirror) and whose last steps add DPP copies;
-//     the wavefronts' sums are added in LDS in a fixed order (deterministic).
+//     reduced by halving steps (permlane32/16 swaps, a DPP mirror) to eight
+//     partial sums per value, stored to LDS; the output stage adds them and the
+//     wavefronts' sums in a fixed order (deterministic, no atomics).
 
 // One step of a chain with the staged coefficients q = (alpha, beta, delta+,
 // delta-) of the degree, delta+- = alpha +- beta - 2 (the difference form's
