@@ -245,6 +245,17 @@ def random_alm(lmax: int, mmax: int, ntrans: int = 1, spin: int = 0,
     ncomp = 2 if spin else 1
     ls, ms = lm_arrays(lmax, mmax)
     n = ls.shape[0]
+    if spectrum == "uniform":
+        # Re and Im uniform on [-1, 1), Im a_l0 = 0 (the accuracy tests' coefficients)
+        out = np.empty((ntrans, ncomp, n, 2))
+        for t in range(ntrans):
+            for c in range(ncomp):
+                rng = np.random.default_rng([SEED_ROOT, tag, t, c])
+                out[t, c] = rng.uniform(-1.0, 1.0, (n, 2))
+        out[..., 1] = np.where(ms == 0, 0.0, out[..., 1])
+        if spin:
+            out[:, :, ls < spin, :] = 0.0
+        return out
     if spectrum == "unit":
         sd_re = np.ones(n)
         sd_im = np.where(ms == 0, 0.0, 1.0)
