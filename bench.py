@@ -27,6 +27,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -88,6 +89,16 @@ def per_degree_rel(x, ref, lmax):
     pd = np.where(den > 0, np.sqrt(num / np.where(den > 0, den, 1.0)), 0.0)
     pd[:2] = 0.0
     return float(pd.max()), int(np.argmax(pd))
+
+
+def pair_errors(a, back):
+    """Errors of a synthesis-analysis pair as Sect. 5 defines them: the relative rms
+    error over all stored coefficients and the largest absolute error of one."""
+    d = (back - a).ravel()
+    rms = math.sqrt(float(np.dot(d, d)) / float(np.dot(a.ravel(), a.ravel())))
+    d = d.reshape(a.shape)
+    mx = float(np.sqrt(np.max(d[..., 0] ** 2 + d[..., 1] ** 2)))
+    return {"eps_rms": rms, "eps_max": mx}
 
 
 def kernel_sources_hash():
@@ -356,7 +367,11 @@ def run_gl4095s2(args):
     out["ring_fft_hbm"] = fft_hbm(p64, k64)
     if j1:
         out["simultaneous_transforms"] = j1
+    # the pair's own round trip (exact quadrature on this grid)
+    out["sht_pair_errors"] = {"fp64": pair_errors(a, alm64_h),
+                              "inputs": "the timed pair's power-law a_lm, C_l = 1/(l+1)^2"}
     if not args.no_fp32:
+        out["sht_pair_errors"]["fp32_mfma"] = pair_errors(a, alm32_h)
         out["kernels_ms"]["fp32_mfma"] = k32
         pd, pl = per_degree_rel(alm32_h, alm64_h, lmax)
         out["fp32_mfma"] = {"value": ntrans / (ms32 * 1e-3), "unit": "pairs/s", "ms_per_step": ms32,
