@@ -885,8 +885,9 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             double2 a, b;
         };
         batched_loop<false, LOOP_U>(max(mva, mvb) + 1, [&](int m) {
-            const int k = m % N;
-            const int kc = (N - k) % N;
+            // bins of m and -m; a division only for aliased terms (m >= N)
+            const int k = m < N ? m : m % N;
+            const int kc = k == 0 ? 0 : N - k;
             const double2 Zk = rd(k), Zc = cconj(rd(kc));
             const double2 dd = csub(Zk, Zc);
             const double2 Sa = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
@@ -909,11 +910,11 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
         const double w = use_weights ? fv.weight[y] : 1.0;
         double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
         batched_loop<false, LOOP_U>(mv + 1, [&](int m) {
-            int k = m % N;
+            int k = m < N ? m : m % N;
             const bool cj = k > h;                   // X_{N-k} = conj X_k
             if (cj) k = N - k;
             // X_k = E_k + e^{-2 pi i k/N} O_k, E/O from Z_k and conj Z_{h-k} (indices mod h)
-            const int k1 = k % h, k2 = (h - k) % h;
+            const int k1 = k == h ? 0 : k, k2 = k1 == 0 ? 0 : h - k1;
             const double2 Zk = rd(k1), Zc = cconj(rd(k2));
             const double2 E = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
             const double2 dd = csub(Zk, Zc);
