@@ -9,7 +9,8 @@ with lmax and the largest error about as lmax^(3/2), for spin 0 and likewise
 for spins 2 and 37.  Its values are plotted, not printed, so the gates take
 those growth laws with a constant of one unit roundoff u = 2^-53:
 eps_rms <= u (lmax + 1) and eps_max <= u (lmax + 1)^(3/2).  The vector kernels
-(one transform) and the matrix-core kernels (several) are both covered."""
+(one transform) and the matrix-core kernels (several) are both covered; the FP32
+matrix-core form is held to its own relative accuracy of 1e-6."""
 import math
 
 import numpy as np
@@ -54,3 +55,19 @@ def test_sht_pair_errors(spin, lmax, ntrans):
           f"eps_max {mx:.3e} ({mx / (U * (lmax + 1) ** 1.5):.3f} u (lmax+1)^1.5)")
     assert rms <= U * (lmax + 1)
     assert mx <= U * (lmax + 1) ** 1.5
+
+
+@pytest.mark.parametrize("spin,lmax,ntrans", [(0, 2047, 8), (2, 1023, 16), (2, 4095, 4)])
+def test_sht_pair_errors_fp32_form(spin, lmax, ntrans):
+    """The same experiment in the FP32 matrix-core form: relative rms error of the
+    pair within 1e-6, the form's accuracy target (FP32 products of FP64 values,
+    FP64 accumulation carried every few chunks)."""
+    sht = _sht()
+    geom = sht.Geometry.reduced_gauss(lmax + 1, 2 * lmax + 2, lmax, lmax, spin, 0.0)
+    plan = sht.Plan(geom, lmax, spin=spin, ntrans=ntrans, precision="fp32_mfma")
+    a = si.random_alm(lmax, lmax, ntrans, spin, spectrum="uniform", tag=950 + spin)
+    print(f"\nfp32 form: spin {spin} lmax {lmax} transforms {ntrans}", flush=True)
+    back = to_host(plan.map2alm(plan.alm2map(to_dev(a))))
+    rms, mx = _pair_errors(a, back)
+    print(f"eps_rms {rms:.3e}, eps_max {mx:.3e}")
+    assert rms <= 1e-6
