@@ -123,7 +123,11 @@ __device__ __forceinline__ double2 cmul_mi(double2 a, bool fwd)
 // GUARD = false: put also runs for clamped indices (it must then be a plain
 // store of get's value, which the owner of count - 1 stores too); GUARD = true
 // (read-modify-write of shared data): put runs for n < count only.
+// The synthesis kernels take four elements per thread at a time; the analysis
+// kernels (two map reads per element in, two phase stores per element out)
+// take two, which measured faster for them at the 8191-point rings.
 constexpr int LOOP_U = 4;
+constexpr int LOOP_U_ANAL = 2;
 template <bool GUARD, int U, typename Get, typename Put>
 __device__ __forceinline__ void batched_loop(int count, Get get, Put put)
 {
@@ -732,8 +736,8 @@ struct SpecRead {
 };
 
 // Runs the length-L transform of the row in LDS.  load(n), n < L, gives the
-// input.  Returns the reader of the result in natural frequency order.
-template <int MODE, bool POW2, typename Load>
+// input (read UI elements per thread at a time).  Returns the reader of the result in natural frequency order.
+template <int MODE, bool POW2, int UI = LOOP_U, typename Load>
 __device__ __forceinline__ SpecRead<MODE, lds_pad<MODE, POW2>()> ring_transform(double2 *buf, const FftView &fv,
                                                          const FftLen &d, bool fwd, Load load)
 {
@@ -744,7 +748,7 @@ __device__ __forceinline__ SpecRead<MODE, lds_pad<MODE, POW2>()> ring_transform(
         bluestein_split<FFT_NREG, POW2>(buf, fv, d, fwd, load);
     } else if constexpr (MODE == KMODE_RADER) {
         const int *rp = fv.itab + d.rpos;   // x_n goes straight to its place in Rader's order
-        batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[padi<POW2>(rp[n])] = v; });
+        batched_loop<false, UI>(L, load, [&](int n, double2 v) { buf[padi<POW2>(rp[n])] = v; });
         __syncthreads();
         const RaderEnds e = rader<POW2>(buf, fv, d, fwd);
         r.x0 = e.x0;
@@ -755,11 +759,11 @@ __device__ __forceinline__ SpecRead<MODE, lds_pad<MODE, POW2>()> ring_transform(
         if (direct && !fwd) {
             // inverse: spectrum in at digit-reversed positions, signal out natural
             const int *pos = fv.itab + in.pos;
-            batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[PADI(pos[n])] = v; });
+            batched_loop<false, UI>(L, load, [&](int n, double2 v) { buf[PADI(pos[n])] = v; });
             __syncthreads();
             fft_dit<POW2>(buf, in, false, fv.ctab);
         } else {
-            batched_loop<false, LOOP_U>(L, load, [&](int n, double2 v) { buf[PADI(n)] = v; });
+            batched_loop<false, UI>(L, load, [&](int n, double2 v) { buf[PADI(n)] = v; });
             __syncthreads();
             if (direct) {
                 fft_dif<POW2>(buf, in, true, fv.ctab);
@@ -872,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
             const double b = pb[(int64_t)x * st];
             return make_double2(pa[(int64_t)x * st], hb ? b : 0.0);
         };
-        const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
+        const auto rd = ring_transform<MODE, POW2, LOOP_U_ANAL>(buf, fv, d, true, xin);
         // ring a: (Zk + conj Z_(N-k)) / 2, ring b: (Zk - conj Z_(N-k)) / (2i), both
         // from one read of the two bins
         const bool hasb = row.yb >= 0;
@@ -884,7 +888,7 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
         struct GPair {
             double2 a, b;
         };
-        batched_loop<false, LOOP_U>(max(mva, mvb) + 1, [&](int m) {
+        batched_loop<false, LOOP_U_ANAL>(max(mva, mvb) + 1, [&](int m) {
             // bins of m and -m; a division only for aliased terms (m >= N)
             const int k = m < N ? m : m % N;
             const int kc = k == 0 ? 0 : N - k;
@@ -903,13 +907,13 @@ __global__ __launch_bounds__(1024) void k_ring_anal(FftView fv, const int *__res
         const double *pa = mp + fv.ofs[row.ya];
         const int64_t st = fv.stride;
         auto xin = [&](int n) { return make_double2(pa[(int64_t)(2 * n) * st], pa[(int64_t)(2 * n + 1) * st]); };
-        const auto rd = ring_transform<MODE, POW2>(buf, fv, d, true, xin);
+        const auto rd = ring_transform<MODE, POW2, LOOP_U_ANAL>(buf, fv, d, true, xin);
         const double2 *htw = fv.ctab + row.half_tw;   // e^{-2 pi i k/N}, k < h
         const int y = row.ya;
         const int mv = min(fv.mvalid[y], fv.mmax);
         const double w = use_weights ? fv.weight[y] : 1.0;
         double2 *G = reinterpret_cast<double2 *>(phase) + (rowF + y) * (fv.mmax + 1);
-        batched_loop<false, LOOP_U>(mv + 1, [&](int m) {
+        batched_loop<false, LOOP_U_ANAL>(mv + 1, [&](int m) {
             int k = m < N ? m : m % N;
             const bool cj = k > h;                   // X_{N-k} = conj X_k
             if (cj) k = N - k;
