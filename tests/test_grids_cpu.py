@@ -79,3 +79,20 @@ def test_reduced_gauss_saves_pixels():
     g = si.reduced_gauss_geometry(4096, 8192, 4095, 4095, 0)
     assert 1.0 - g.nphi.sum() / (4096 * 8191) > 0.30
     assert g.nphi[2048] == 8192 and g.nphi[0] < 300
+
+
+@pytest.mark.parametrize("spin", [0, 2, 37])
+def test_uniform_coefficients_recipe(spin):
+    """The accuracy test's coefficients: Re and Im uniform on [-1, 1), Im a_l0 = 0,
+    l < spin zero, seeded (two calls agree, another tag differs)."""
+    lmax = 63
+    a = si.random_alm(lmax, lmax, 2, spin, spectrum="uniform", tag=5)
+    ls, ms = si.lm_arrays(lmax, lmax)
+    assert a.shape == (2, 2 if spin else 1, ls.size, 2)
+    assert np.all(a >= -1.0) and np.all(a < 1.0)
+    assert np.all(a[:, :, ms == 0, 1] == 0.0)
+    assert np.all(a[:, :, ls < spin, :] == 0.0)
+    live = a[:, :, (ls >= spin) & (ms > 0), :]
+    assert abs(live.mean()) < 0.02 and abs(live.var() - 1.0 / 3.0) < 0.02   # U(-1, 1): mean 0, variance 1/3
+    assert np.array_equal(a, si.random_alm(lmax, lmax, 2, spin, spectrum="uniform", tag=5))
+    assert not np.array_equal(a, si.random_alm(lmax, lmax, 2, spin, spectrum="uniform", tag=6))
